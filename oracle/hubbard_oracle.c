@@ -505,7 +505,8 @@ int orc_lanczos(const orc_model *m, const double *f1, double tol, int max_iter,
         /* Ritz value of T_j (diagonal a_1..a_j, off-diagonal b_2..b_j) */
         double e = orc_tridiag_min(a, boff + 1, j);
         e_hist[j - 1] = e;
-        if (j >= 2 && fabs(e - e_last) <= tol * fmax(1.0, fabs(e))) {
+        /* a negative tol switches the energy test off (fixed iteration count) */
+        if (tol >= 0.0 && j >= 2 && fabs(e - e_last) <= tol * fmax(1.0, fabs(e))) {
             res->converged = 1;
             break;
         }
