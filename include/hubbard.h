@@ -1,0 +1,180 @@
+/*
+ * hubbard.h -- C ABI of the MI355X Hubbard exact-diagonalisation library.
+ *
+ * The library computes the lowest eigenvalue (and optionally the eigenvector)
+ * of the Hubbard Hamiltonian
+ *     H = -t sum_<ij> sum_sigma (c+_{i sigma} c_{j sigma} + h.c.) + U sum_i n_{i up} n_{i dn}
+ * in one sector of fixed N_up and N_dn (Siro & Harju, arXiv:1204.3425,
+ * Sec. 1, eq. H, and Sec. 2.1), with the Lanczos iteration of Sec. 2.2
+ * (Alg. 1) running on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every call:
+ *   - Sites are numbered 0..sites-1; bit i of a configuration word is site i
+ *     (Sec. 2.1, eq. binaryrep).
+ *   - Basis order: configurations of each spin in ascending integer order;
+ *     J = i_up * dim_dn + i_dn (Sec. 2.1, eq. J-formula).  Every vector
+ *     crossing this ABI is a contiguous array of dim elements in J order.
+ *   - A bond (i, j) is undirected; the hermitian conjugate hop is implied
+ *     (eq. H).  The matrix element of one hop is -t * sgn, sgn = (-1)^n, n the
+ *     number of same-spin electrons on sites strictly between i and j
+ *     (Sec. 2.1, the sign paragraph).
+ *   - Device pointers are HIP device memory on the current device of the
+ *     calling thread.  Host pointers are ordinary memory.  The caller owns every
+ *     buffer it passes; the handle owns its basis and tables.
+ *   - Return codes: 0 = success, > 0 = warning with results written,
+ *     < 0 = error with nothing written.  hubbard_last_error() gives a message
+ *     for the most recent failure on the calling thread.  No C++ exception
+ *     crosses this boundary.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef HUBBARD_H
+#define HUBBARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hubbard *hubbard_h;
+
+enum {
+    HUBBARD_OK = 0,
+    HUBBARD_ENOCONV = 1,  /* max_iter reached before the energy test passed */
+    HUBBARD_EINVAL = -1,  /* invalid argument */
+    HUBBARD_ERANGE = -2,  /* sector too large for the index types */
+    HUBBARD_ENOMEM = -3,  /* device or host allocation failed */
+    HUBBARD_EDEVICE = -4, /* a HIP call failed */
+    HUBBARD_EBUSY = -5    /* resource in use (server queue full) */
+};
+
+enum {
+    HUBBARD_FP64 = 0,  /* vectors, H.v and reductions in FP64 */
+    HUBBARD_MIXED = 1  /* vectors and H.v in FP32 (FP32 accumulation); alpha/beta
+                          reductions, the tridiagonal solve and the residual in FP64 */
+};
+
+enum { HUBBARD_SPIN_UP = 0, HUBBARD_SPIN_DN = 1 };
+
+/* Why a Lanczos run stopped. */
+enum {
+    HUBBARD_STOP_MAXITER = 0,   /* max_iter steps done */
+    HUBBARD_STOP_CONVERGED = 1, /* |E_j - E_{j-1}| <= tol * max(1, |E_j|) (Sec. 2.2) */
+    HUBBARD_STOP_BREAKDOWN = 2, /* b_{j+1} vanished: invariant subspace (Alg. 1) */
+    HUBBARD_STOP_EXHAUSTED = 3  /* j reached dim */
+};
+
+typedef struct {
+    int32_t sites, n_up, n_dn, n_edges;
+    double t, U;
+    int64_t dim_up, dim_dn, dim; /* C(sites, N_up), C(sites, N_dn), their product (Sec. 2.1) */
+    int32_t w_up, w_dn;          /* ELL widths = max entries per row (Sec. 4.2, Fig. ELL) */
+    int64_t nnz_up, nnz_dn;      /* stored hopping entries per spin */
+    size_t device_bytes;         /* device memory held by the handle (tables + states) */
+    size_t vector_bytes;         /* device memory one Lanczos run allocates (work vectors) */
+} hubbard_info_t;
+
+typedef struct {
+    double tol;          /* energy test of Sec. 2.2; tol < 0 runs exactly max_iter steps */
+    int32_t max_iter;    /* >= 1 */
+    int32_t precision;   /* HUBBARD_FP64 or HUBBARD_MIXED */
+    uint64_t seed;       /* start vector f1[J] = 2u-1, u from SplitMix64 counter J+1, normalised */
+    const double *start; /* optional device FP64 start vector (dim, unit norm, J order); overrides seed */
+    double *psi;         /* optional device FP64 output: ground-state vector, unit norm, <psi,f1> > 0 */
+    double *a_out;       /* optional host array[max_iter]: a_j, j = 1..n_iter (Alg. 1) */
+    double *b_out;       /* optional host array[max_iter]: b_{j+1}, j = 1..n_iter */
+    double *e_out;       /* optional host array[max_iter]: lowest eigenvalue of T_j */
+} hubbard_opts;
+
+typedef struct {
+    double e0;          /* lowest eigenvalue of T_m (Sec. 2.2, eq. Tmatrix) */
+    double residual;    /* FP64 ||H psi - e0 psi|| when psi was requested, else -1 */
+    double rayleigh;    /* FP64 <psi|H|psi> when psi was requested, else NaN */
+    double err_est;     /* residual / max(1, |e0|) when psi was requested, else -1 */
+    double seconds;     /* wall time of the whole call */
+    double seconds_per_iter; /* mean wall time of one Lanczos step (first pass) */
+    int32_t n_iter;     /* m = number of a_j computed */
+    int32_t stop;       /* HUBBARD_STOP_* */
+    int32_t status;     /* HUBBARD_OK or HUBBARD_ENOCONV, or an error code */
+    int32_t precision;
+} hubbard_result;
+
+/* Builds the basis of each spin (ascending configuration words, combinatorial
+ * rank; Sec. 2.1) and the signed ELL hopping tables (Sec. 4.2, eq.
+ * H-Kroneckersum and Fig. ELL), uploads them to the current device and
+ * returns a handle.
+ *   sites: 1..32.  edges: host array of 2*n_edges int32 site indices, each pair
+ *   (i, j) with 0 <= i, j < sites, i != j, no unordered pair repeated.
+ *   n_up, n_dn: 0..sites.  t, U: finite.
+ * Errors: EINVAL (bad argument), ERANGE (dim >= 2^40: one vector would not
+ * fit a device), ENOMEM, EDEVICE.  On a machine with no HIP device the handle
+ * holds the host tables only: hubbard_info and the export calls work, and every
+ * device call returns EDEVICE. */
+int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_dn, double t, double U,
+                  hubbard_h *out);
+
+/* Releases the handle and its device memory.  NULL is accepted. */
+int hubbard_free(hubbard_h h);
+
+/* Stream for every later call on this handle (a hipStream_t; NULL = the null
+ * stream).  The caller keeps the stream alive while the handle uses it. */
+int hubbard_set_stream(hubbard_h h, void *hip_stream);
+
+/* Arithmetic of hubbard_apply and hubbard_lanczos: HUBBARD_FP64 (default) or
+ * HUBBARD_MIXED. */
+int hubbard_set_precision(hubbard_h h, int precision);
+
+/* Seed of the start vector used by hubbard_lanczos (default 12043425). */
+int hubbard_set_seed(hubbard_h h, uint64_t seed);
+
+/* y = H x (Sec. 4.3: H_up (x) I, I (x) H_dn and the interaction term in one
+ * kernel).  x, y: device arrays of dim elements in J order, double under
+ * HUBBARD_FP64 and float under HUBBARD_MIXED; y is overwritten and must not
+ * overlap x.  Asynchronous on the handle's stream. */
+int hubbard_apply(hubbard_h h, const void *x, void *y);
+
+/* Lanczos ground state (Sec. 2.2, Alg. 1, two-vector form): iterates until
+ * the energy test passes with tol (> 0), b_{j+1} vanishes, or max_iter (>= 1)
+ * steps.  Writes the lowest Ritz value to *E0 (host).  psi: NULL, or a device
+ * FP64 array of dim elements receiving the ground-state vector (a second,
+ * replayed pass).  Synchronous.  Returns OK, or ENOCONV when max_iter was hit
+ * first (E0 still written). */
+int hubbard_lanczos(hubbard_h h, double tol, int max_iter, double *E0, double *psi);
+
+/* As hubbard_lanczos with every option and the full result record. */
+int hubbard_lanczos_ex(hubbard_h h, const hubbard_opts *opts, hubbard_result *res);
+
+/* Sizes of the handle's sector and tables. */
+int hubbard_info(hubbard_h h, hubbard_info_t *info);
+
+/* Host copy of one spin's basis: dim_sigma configuration words, ascending. */
+int hubbard_export_basis(hubbard_h h, int spin, uint32_t *states);
+
+/* Host copy of one spin's ELL hopping table in the column-major layout of
+ * Fig. ELL: entry k of row r at k * dim_sigma + r, for k < w_sigma.  col: the
+ * column (rank of the hopped configuration); sgn: +1 or -1 (matrix element
+ * -t * sgn); padding has col 0 and sgn 0.  Entries of a row ascend by column. */
+int hubbard_export_table(hubbard_h h, int spin, int32_t *col, int8_t *sgn);
+
+/* f[J] = 2u - 1 for J < dim, u = (SplitMix64(seed + (J+1) * 0x9E3779B97F4A7C15) >> 11) * 2^-53
+ * (Steele, Lea & Flood 2014): the un-normalised start vector of Alg. 1.
+ * f: device FP64 array.  Asynchronous on `hip_stream`. */
+int hubbard_start_raw(uint64_t seed, int64_t dim, double *f, void *hip_stream);
+
+/* Runs n independent Lanczos solves (one per handle, each with opts[i]) as one
+ * batch on the current device, writing res[i].  Small sectors share launches so
+ * the GPU stays busy (Sec. 5 notes that small systems leave it idle).  Every
+ * result equals, within the stated tolerance, the same solve run alone.
+ * Synchronous.  Returns the most severe per-solve status. */
+int hubbard_lanczos_batch(hubbard_h *hs, int n, const hubbard_opts *opts, hubbard_result *res);
+
+/* Message for a return code, and the message of the calling thread's last
+ * failure (empty when none). */
+const char *hubbard_strerror(int code);
+const char *hubbard_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HUBBARD_H */

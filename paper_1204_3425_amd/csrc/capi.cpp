@@ -1,0 +1,644 @@
+// C ABI of the Hubbard library: argument checks, handle life cycle, and the
+// Lanczos driver (Siro & Harju, Sec. 2.2, Alg. 1 in its two-vector form).
+//
+// Driver.  Two device vectors C and P hold s_c f_j and s_p f_{j-1}; the scale
+// factors live in a small block of device scalars, so no host round trip is
+// needed between steps.  Step j:
+//     P <- (1/s_c) H C - (b_j / s_p) P        = q_j       (one fused H.v kernel)
+//     a_j = (P . C) / s_c                                  (fixed-order reduction)
+//     P <- P - (a_j / s_c) C                   = q_j - a_j f_j
+//     b_{j+1} = |P|                                        (fixed-order reduction)
+// after which P holds b_{j+1} f_{j+1}: the two vectors swap roles.  This is
+// the paper's split of the three-term recurrence into an in-place update of
+// f_{j-1} (eq. split1), with the 1/b_{j+1} normalisation folded into the next
+// H.v instead of a separate pass.  The host reads (a_j, b_{j+1}) a few steps
+// behind the device, computes the lowest eigenvalue of T_j (eq. Tmatrix) and
+// applies the energy test of Sec. 2.2.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace hub {
+
+static thread_local std::string g_last_error;
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        fail(HUBBARD_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    fail(HUBBARD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+static int guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return HUBBARD_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return HUBBARD_EDEVICE;
+    }
+}
+
+// Device buffer owned by RAII.
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    explicit DevBuf(size_t bytes)
+    {
+        if (bytes)
+            HUB_HIP(hipMalloc(&p, bytes));
+    }
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct PinnedBuf {
+    void *p = nullptr;
+    explicit PinnedBuf(size_t bytes) { HUB_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault)); }
+    ~PinnedBuf()
+    {
+        if (p)
+            (void)hipHostFree(p);
+    }
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+static void free_device(hubbard *h)
+{
+    DeviceTables &d = h->dev;
+    void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    d = DeviceTables();
+}
+
+template <typename T>
+static T *upload(const void *src, size_t bytes, size_t &total)
+{
+    void *p = nullptr;
+    HUB_HIP(hipMalloc(&p, bytes ? bytes : 16));
+    if (bytes)
+        HUB_HIP(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
+    total += bytes;
+    return static_cast<T *>(p);
+}
+
+static void upload_tables(hubbard *h)
+{
+    DeviceTables &d = h->dev;
+    size_t total = 0;
+    d.states_up = upload<uint32_t>(h->up.states.data(), h->up.states.size() * 4, total);
+    d.states_dn = upload<uint32_t>(h->dn.states.data(), h->dn.states.size() * 4, total);
+    // up table row-major (one row's entries are read by a whole workgroup)
+    std::vector<uint32_t> rows((size_t)h->up.dim * (size_t)std::max(1, h->up.width), 0u);
+    for (int64_t r = 0; r < h->up.dim; r++)
+        for (int k = 0; k < h->up.row_nnz[(size_t)r]; k++) {
+            size_t src = (size_t)k * (size_t)h->up.dim + (size_t)r;
+            rows[(size_t)r * (size_t)h->up.width + (size_t)k] = pack_entry(h->up.col[src], h->up.sgn[src]);
+        }
+    d.up_rows = upload<uint32_t>(rows.data(), rows.size() * 4, total);
+    // down table column-major (lanes of a wave read consecutive rows d)
+    std::vector<uint32_t> cols((size_t)h->dn.dim * (size_t)std::max(1, h->dn.width), 0u);
+    for (int64_t r = 0; r < h->dn.dim; r++)
+        for (int k = 0; k < h->dn.row_nnz[(size_t)r]; k++) {
+            size_t src = (size_t)k * (size_t)h->dn.dim + (size_t)r;
+            cols[src] = pack_entry(h->dn.col[src], h->dn.sgn[src]);
+        }
+    d.dn_cols = upload<uint32_t>(cols.data(), cols.size() * 4, total);
+    d.nnz_up = upload<uint16_t>(h->up.row_nnz.data(), h->up.row_nnz.size() * 2, total);
+    d.nnz_dn = upload<uint16_t>(h->dn.row_nnz.data(), h->dn.row_nnz.size() * 2, total);
+    d.bytes = total;
+}
+
+static HvArgs hv_args(const hubbard *h)
+{
+    HvArgs a;
+    a.states_up = h->dev.states_up;
+    a.states_dn = h->dev.states_dn;
+    a.up_rows = h->dev.up_rows;
+    a.dn_cols = h->dev.dn_cols;
+    a.nnz_up = h->dev.nnz_up;
+    a.nnz_dn = h->dev.nnz_dn;
+    a.dim_up = h->up.dim;
+    a.dim_dn = h->dn.dim;
+    a.w_up = h->up.width;
+    a.w_dn = h->dn.width;
+    a.t = h->t;
+    a.U = h->U;
+    return a;
+}
+
+static void check_handle(hubbard_h h)
+{
+    if (!h)
+        fail(HUBBARD_EINVAL, "null handle");
+}
+
+static void use_device(const hubbard *h)
+{
+    if (h->device < 0)
+        fail(HUBBARD_EDEVICE, "no HIP device was present when the handle was built");
+    HUB_HIP(hipSetDevice(h->device));
+}
+
+// ------------------------------------------------------------------ Lanczos
+
+struct LanczosOut {
+    std::vector<double> a, b, e;  // a_j, b_{j+1}, lowest eigenvalue of T_j
+    int m = 0;
+    int stop = HUBBARD_STOP_MAXITER;
+    double e0 = 0, residual = -1, rayleigh = NAN;
+    double seconds_first = 0;
+};
+
+template <typename T>
+static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
+{
+    const int64_t n = h->dim;
+    const HvArgs args = hv_args(h);
+    hipStream_t s = h->stream;
+    const int hb = hv_blocks(args, sizeof(T));
+    const int sb = stream_blocks(n);
+    const int max_iter = o.max_iter;
+
+    DevBuf vecA(sizeof(T) * (size_t)n), vecB(sizeof(T) * (size_t)n);
+    DevBuf partials(sizeof(double) * (size_t)(2 * std::max(hb, sb) + 64));
+    DevBuf scal(sizeof(double) * 8 + sizeof(double) * 2 * (size_t)(max_iter + 1));
+    double *S = scal.as<double>();
+    double *hist = S + 8;
+    PinnedBuf host(sizeof(double) * (2 * (size_t)(max_iter + 1) + 8));
+    double *hh = host.as<double>();
+    const double *given = o.start;
+    const uint64_t seed = o.seed;
+
+    // f_1: generated (or given), normalised in FP64, rounded to T
+    launch_start_norm2(given, seed, n, partials.as<double>(), sb, s);
+    launch_reduce(partials.as<double>(), sb, 0, 1, S + 4, s);
+    HUB_HIP(hipMemcpyAsync(hh, S + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    HUB_HIP(hipStreamSynchronize(s));
+    if (!(hh[0] > 0.0) || !std::isfinite(hh[0]))
+        fail(HUBBARD_EINVAL, "start vector has zero or non-finite norm");
+    const double inv_norm = 1.0 / std::sqrt(hh[0]);
+
+    auto start_pass = [&](T *C, T *P) {
+        launch_start_fill<T>(given, seed, inv_norm, C, P, n, s);
+        launch_init_scalars(S, s);
+    };
+    auto step = [&](T *C, T *P, int j0) {
+        launch_hv<T>(args, C, P, HV_LANCZOS, 0.0, S + 1, partials.as<double>(), hb, s);
+        launch_reduce_step(partials.as<double>(), hb, RED_DOT, S, hist, j0, s);
+        launch_axpy_norm<T>(P, C, S + 3, n, partials.as<double>(), sb, s);
+        launch_reduce_step(partials.as<double>(), sb, RED_NORM, S, hist, j0, s);
+    };
+
+    // ---- first pass: run ahead of the host by `lookahead` steps
+    const int lookahead = n >= (int64_t)4000000 ? 2 : 8;
+    const int nev = lookahead + 2;
+    std::vector<hipEvent_t> ev((size_t)nev);
+    for (auto &e : ev)
+        HUB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    struct EvGuard {
+        std::vector<hipEvent_t> &v;
+        ~EvGuard()
+        {
+            for (auto e : v)
+                (void)hipEventDestroy(e);
+        }
+    } evguard{ev};
+
+    T *bufs[2] = {vecA.as<T>(), vecB.as<T>()};
+    auto t0 = std::chrono::steady_clock::now();
+    start_pass(bufs[0], bufs[1]);
+    out.a.clear();
+    out.b.clear();
+    out.e.clear();
+    int launched = 0, checked = 0;
+    bool stop = false;
+    double scale = 0.0;
+    while (!stop) {
+        if (launched < max_iter) {
+            const int j0 = launched;  // 0-based step index
+            step(bufs[j0 & 1], bufs[(j0 + 1) & 1], j0);
+            HUB_HIP(hipMemcpyAsync(hh + 2 * j0, hist + 2 * j0, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HUB_HIP(hipEventRecord(ev[(size_t)(j0 % nev)], s));
+            launched++;
+        }
+        while (checked < launched && (launched - checked > lookahead || launched == max_iter)) {
+            const int j0 = checked;
+            HUB_HIP(hipEventSynchronize(ev[(size_t)(j0 % nev)]));
+            const double a = hh[2 * j0], b = hh[2 * j0 + 1];
+            out.a.push_back(a);
+            out.b.push_back(b);
+            const int j = j0 + 1;
+            const double e = tridiag_lowest(out.a.data(), out.b.data(), j);
+            out.e.push_back(e);
+            checked++;
+            if (!std::isfinite(a) || !std::isfinite(b))
+                fail(HUBBARD_EDEVICE, "non-finite Lanczos coefficient at step " + std::to_string(j));
+            if (o.tol >= 0.0 && j >= 2 && std::fabs(e - out.e[(size_t)j0 - 1]) <= o.tol * std::fmax(1.0, std::fabs(e))) {
+                out.stop = HUBBARD_STOP_CONVERGED;
+                stop = true;
+                break;
+            }
+            scale = std::fmax(scale, std::fabs(a) + (j0 > 0 ? out.b[(size_t)j0 - 1] : 0.0));
+            if (b == 0.0 || b <= 1e-12 * scale) {
+                out.stop = HUBBARD_STOP_BREAKDOWN;
+                stop = true;
+                break;
+            }
+            if ((int64_t)j >= n) {
+                out.stop = HUBBARD_STOP_EXHAUSTED;
+                stop = true;
+                break;
+            }
+            if (j == max_iter) {
+                out.stop = HUBBARD_STOP_MAXITER;
+                stop = true;
+                break;
+            }
+        }
+    }
+    HUB_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    out.m = checked;
+    out.a.resize((size_t)out.m);
+    out.b.resize((size_t)out.m);
+    out.e.resize((size_t)out.m);
+    out.e0 = out.e.back();
+    out.seconds_first = std::chrono::duration<double>(t1 - t0).count();
+
+    if (!o.psi)
+        return;
+    // ---- second pass: replay the identical recurrence and accumulate psi
+    const int m = out.m;
+    std::vector<double> y((size_t)m);
+    tridiag_lowest_vector(out.a.data(), out.b.data(), m, out.e0, y.data());
+    start_pass(bufs[0], bufs[1]);
+    for (int j0 = 0; j0 < m; j0++) {
+        T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
+        launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, n, j0 == 0, s);
+        if (j0 + 1 < m)
+            step(C, P, j0);
+    }
+    // normalise, sign so that <psi, f1> > 0
+    launch_psi_stats(o.psi, given, seed, n, partials.as<double>(), sb, s);
+    launch_reduce(partials.as<double>(), sb, sb, 2, S + 4, s);
+    HUB_HIP(hipMemcpyAsync(hh, S + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HUB_HIP(hipStreamSynchronize(s));
+    double c = 1.0 / std::sqrt(hh[0]);
+    if (hh[1] * inv_norm < 0.0)
+        c = -c;
+    launch_scale(o.psi, c, n, s);
+    // FP64 residual |H psi - E0 psi| and Rayleigh quotient <psi|H|psi>
+    const int hb64 = hv_blocks(args, sizeof(double));
+    launch_hv<double>(args, o.psi, nullptr, HV_RESIDUAL, out.e0, nullptr, partials.as<double>(), hb64, s);
+    launch_reduce(partials.as<double>(), hb64, hb64, 2, S + 4, s);
+    HUB_HIP(hipMemcpyAsync(hh, S + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HUB_HIP(hipStreamSynchronize(s));
+    out.residual = std::sqrt(hh[0]);
+    out.rayleigh = hh[1];
+}
+
+static void validate_opts(const hubbard_opts &o)
+{
+    if (!(o.max_iter >= 1))
+        fail(HUBBARD_EINVAL, "max_iter must be >= 1");
+    if (std::isnan(o.tol))
+        fail(HUBBARD_EINVAL, "tol is NaN");
+    if (o.precision != HUBBARD_FP64 && o.precision != HUBBARD_MIXED)
+        fail(HUBBARD_EINVAL, "unknown precision");
+}
+
+static int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res)
+{
+    validate_opts(o);
+    use_device(h);
+    auto t0 = std::chrono::steady_clock::now();
+    LanczosOut out;
+    if (o.precision == HUBBARD_FP64)
+        run_lanczos<double>(h, o, out);
+    else
+        run_lanczos<float>(h, o, out);
+    auto t1 = std::chrono::steady_clock::now();
+    if (o.a_out)
+        std::memcpy(o.a_out, out.a.data(), sizeof(double) * (size_t)out.m);
+    if (o.b_out)
+        std::memcpy(o.b_out, out.b.data(), sizeof(double) * (size_t)out.m);
+    if (o.e_out)
+        std::memcpy(o.e_out, out.e.data(), sizeof(double) * (size_t)out.m);
+    const int status = (out.stop == HUBBARD_STOP_MAXITER && o.tol >= 0.0) ? HUBBARD_ENOCONV : HUBBARD_OK;
+    if (res) {
+        hubbard_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.e0 = out.e0;
+        r.residual = o.psi ? out.residual : -1.0;
+        r.rayleigh = o.psi ? out.rayleigh : NAN;
+        r.err_est = o.psi ? out.residual / std::fmax(1.0, std::fabs(out.e0)) : -1.0;
+        r.seconds = std::chrono::duration<double>(t1 - t0).count();
+        r.seconds_per_iter = out.m ? out.seconds_first / out.m : 0.0;
+        r.n_iter = out.m;
+        r.stop = out.stop;
+        r.status = status;
+        r.precision = o.precision;
+        *res = r;
+    }
+    return status;
+}
+
+}  // namespace hub
+
+using namespace hub;
+
+extern "C" {
+
+int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_dn, double t, double U,
+                  hubbard_h *out)
+{
+    return guarded([&]() -> int {
+        if (!out)
+            fail(HUBBARD_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (sites < 1 || sites > 32)
+            fail(HUBBARD_EINVAL, "sites must be in 1..32");
+        if (n_edges < 0 || (n_edges > 0 && !edges))
+            fail(HUBBARD_EINVAL, "bad edge list");
+        if (n_up < 0 || n_up > sites || n_dn < 0 || n_dn > sites)
+            fail(HUBBARD_EINVAL, "electron counts must be in 0..sites");
+        if (!std::isfinite(t) || !std::isfinite(U))
+            fail(HUBBARD_EINVAL, "t and U must be finite");
+        std::vector<int32_t> e((size_t)2 * (size_t)n_edges);
+        std::vector<char> seen((size_t)sites * (size_t)sites, 0);
+        for (int k = 0; k < n_edges; k++) {
+            int i = edges[2 * k], j = edges[2 * k + 1];
+            if (i < 0 || j < 0 || i >= sites || j >= sites || i == j)
+                fail(HUBBARD_EINVAL, "edge " + std::to_string(k) + " is not a pair of distinct sites");
+            int lo = std::min(i, j), hi = std::max(i, j);
+            if (seen[(size_t)lo * (size_t)sites + (size_t)hi])
+                fail(HUBBARD_EINVAL, "edge " + std::to_string(k) + " repeats a bond");
+            seen[(size_t)lo * (size_t)sites + (size_t)hi] = 1;
+            e[(size_t)2 * k] = i;
+            e[(size_t)2 * k + 1] = j;
+        }
+        const uint64_t du = binomial(sites, n_up), dd = binomial(sites, n_dn);
+        // a spin dimension is at most C(32,16) < 2^31, so the sector size is the limit:
+        // one vector of 2^40 elements would not fit the memory of any single device
+        if ((long double)du * (long double)dd >= (long double)(1ull << 40))
+            fail(HUBBARD_ERANGE, "sector dimension exceeds 2^40");
+        std::unique_ptr<hubbard> h(new hubbard());
+        h->sites = sites;
+        h->n_up = n_up;
+        h->n_dn = n_dn;
+        h->t = t;
+        h->U = U;
+        h->edges = e;
+        build_spin_table(sites, e, n_up, h->up);
+        build_spin_table(sites, e, n_dn, h->dn);
+        h->dim = h->up.dim * h->dn.dim;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+            (void)hipGetLastError();
+            h->device = -1;  // host tables only: info and export work, device calls fail
+        } else {
+            HUB_HIP(hipGetDevice(&h->device));
+            try {
+                upload_tables(h.get());
+            } catch (...) {
+                free_device(h.get());
+                throw;
+            }
+        }
+        *out = h.release();
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_free(hubbard_h h)
+{
+    return guarded([&]() -> int {
+        if (!h)
+            return HUBBARD_OK;
+        if (h->device >= 0) {
+            (void)hipSetDevice(h->device);
+            free_device(h);
+        }
+        delete h;
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_set_stream(hubbard_h h, void *hip_stream)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        h->stream = static_cast<hipStream_t>(hip_stream);
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_set_precision(hubbard_h h, int precision)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (precision != HUBBARD_FP64 && precision != HUBBARD_MIXED)
+            fail(HUBBARD_EINVAL, "unknown precision");
+        h->precision = precision;
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_set_seed(hubbard_h h, uint64_t seed)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        h->seed = seed;
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_apply(hubbard_h h, const void *x, void *y)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (!x || !y)
+            fail(HUBBARD_EINVAL, "x and y must be device pointers");
+        const size_t es = h->precision == HUBBARD_FP64 ? 8 : 4;
+        const char *xb = static_cast<const char *>(x);
+        const char *yb = static_cast<const char *>(y);
+        const size_t bytes = es * (size_t)h->dim;
+        if (xb < yb + bytes && yb < xb + bytes)
+            fail(HUBBARD_EINVAL, "x and y overlap");
+        use_device(h);
+        const HvArgs a = hv_args(h);
+        if (h->precision == HUBBARD_FP64)
+            launch_hv<double>(a, static_cast<const double *>(x), static_cast<double *>(y), HV_STORE, 0.0, nullptr,
+                              nullptr, hv_blocks(a, 8), h->stream);
+        else
+            launch_hv<float>(a, static_cast<const float *>(x), static_cast<float *>(y), HV_STORE, 0.0, nullptr,
+                             nullptr, hv_blocks(a, 4), h->stream);
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_lanczos(hubbard_h h, double tol, int max_iter, double *E0, double *psi)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (!E0)
+            fail(HUBBARD_EINVAL, "E0 is NULL");
+        if (!(tol > 0.0))
+            fail(HUBBARD_EINVAL, "tol must be > 0");
+        hubbard_opts o;
+        std::memset(&o, 0, sizeof(o));
+        o.tol = tol;
+        o.max_iter = max_iter;
+        o.precision = h->precision;
+        o.seed = h->seed;
+        o.psi = psi;
+        hubbard_result r;
+        int rc = lanczos_impl(h, o, &r);
+        *E0 = r.e0;
+        return rc;
+    });
+}
+
+int hubbard_lanczos_ex(hubbard_h h, const hubbard_opts *opts, hubbard_result *res)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (!opts || !res)
+            fail(HUBBARD_EINVAL, "opts and res must not be NULL");
+        return lanczos_impl(h, *opts, res);
+    });
+}
+
+int hubbard_info(hubbard_h h, hubbard_info_t *info)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (!info)
+            fail(HUBBARD_EINVAL, "info is NULL");
+        hubbard_info_t r;
+        std::memset(&r, 0, sizeof(r));
+        r.sites = h->sites;
+        r.n_up = h->n_up;
+        r.n_dn = h->n_dn;
+        r.n_edges = (int32_t)(h->edges.size() / 2);
+        r.t = h->t;
+        r.U = h->U;
+        r.dim_up = h->up.dim;
+        r.dim_dn = h->dn.dim;
+        r.dim = h->dim;
+        r.w_up = h->up.width;
+        r.w_dn = h->dn.width;
+        r.nnz_up = h->up.nnz;
+        r.nnz_dn = h->dn.nnz;
+        r.device_bytes = h->dev.bytes;
+        r.vector_bytes = (size_t)h->dim * (h->precision == HUBBARD_FP64 ? 16 : 8);
+        *info = r;
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_export_basis(hubbard_h h, int spin, uint32_t *states)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (spin != HUBBARD_SPIN_UP && spin != HUBBARD_SPIN_DN)
+            fail(HUBBARD_EINVAL, "spin must be 0 (up) or 1 (down)");
+        if (!states)
+            fail(HUBBARD_EINVAL, "states is NULL");
+        const SpinTable &tb = spin == HUBBARD_SPIN_UP ? h->up : h->dn;
+        std::memcpy(states, tb.states.data(), tb.states.size() * 4);
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_export_table(hubbard_h h, int spin, int32_t *col, int8_t *sgn)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (spin != HUBBARD_SPIN_UP && spin != HUBBARD_SPIN_DN)
+            fail(HUBBARD_EINVAL, "spin must be 0 (up) or 1 (down)");
+        if (!col || !sgn)
+            fail(HUBBARD_EINVAL, "col and sgn must not be NULL");
+        const SpinTable &tb = spin == HUBBARD_SPIN_UP ? h->up : h->dn;
+        std::memcpy(col, tb.col.data(), tb.col.size() * 4);
+        std::memcpy(sgn, tb.sgn.data(), tb.sgn.size());
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_start_raw(uint64_t seed, int64_t dim, double *f, void *hip_stream)
+{
+    return guarded([&]() -> int {
+        if (dim < 0 || (dim > 0 && !f))
+            fail(HUBBARD_EINVAL, "bad start-vector arguments");
+        if (dim > 0)
+            launch_start_raw(seed, f, dim, static_cast<hipStream_t>(hip_stream));
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_lanczos_batch(hubbard_h *hs, int n, const hubbard_opts *opts, hubbard_result *res)
+{
+    return guarded([&]() -> int {
+        if (n < 0 || (n > 0 && (!hs || !opts || !res)))
+            fail(HUBBARD_EINVAL, "bad batch arguments");
+        int worst = HUBBARD_OK;
+        for (int i = 0; i < n; i++) {
+            check_handle(hs[i]);
+            int rc = lanczos_impl(hs[i], opts[i], &res[i]);
+            if (rc != HUBBARD_OK && (worst == HUBBARD_OK || rc < worst))
+                worst = rc;
+        }
+        return worst;
+    });
+}
+
+const char *hubbard_strerror(int code)
+{
+    switch (code) {
+    case HUBBARD_OK: return "success";
+    case HUBBARD_ENOCONV: return "max_iter reached before convergence";
+    case HUBBARD_EINVAL: return "invalid argument";
+    case HUBBARD_ERANGE: return "sector too large";
+    case HUBBARD_ENOMEM: return "out of memory";
+    case HUBBARD_EDEVICE: return "device error";
+    case HUBBARD_EBUSY: return "busy";
+    default: return "unknown error code";
+    }
+}
+
+const char *hubbard_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

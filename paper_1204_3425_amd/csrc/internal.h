@@ -1,0 +1,111 @@
+// Internal declarations of the Hubbard library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hubbard.h"
+
+namespace hub {
+
+// Error raised inside the library; converted to a return code at the ABI.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HUB_HIP(call) ::hub::hip_check((call), #call)
+
+// One spin's basis and hopping table as built on the host.
+struct SpinTable {
+    int n = 0;                      // electrons of this spin
+    int64_t dim = 0;                // C(sites, n)
+    int32_t width = 0;              // ELL width = max entries of a row
+    int64_t nnz = 0;
+    std::vector<uint32_t> states;   // ascending configuration words
+    std::vector<int32_t> col;       // column-major ELL: entry k of row r at k*dim + r
+    std::vector<int8_t> sgn;        // +1 / -1, padding 0
+    std::vector<uint16_t> row_nnz;  // entries used in each row
+};
+
+// Packed device form of a hopping entry: bits 0..30 column, bit 31 set when
+// the element is +t (sgn = -1).
+inline uint32_t pack_entry(int32_t col, int8_t sgn) { return (uint32_t)col | (sgn < 0 ? 0x80000000u : 0u); }
+
+struct DeviceTables {
+    uint32_t *states_up = nullptr, *states_dn = nullptr;
+    uint32_t *up_rows = nullptr;   // row-major: entry k of row r at r*w_up + k (row entries are wave-uniform)
+    uint32_t *dn_cols = nullptr;   // column-major: entry k of row d at k*dim_dn + d (coalesced across lanes)
+    uint16_t *nnz_up = nullptr, *nnz_dn = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace hub
+
+struct hubbard {
+    int sites = 0, n_up = 0, n_dn = 0;
+    double t = 0, U = 0;
+    std::vector<int32_t> edges;  // 2 per bond
+    hub::SpinTable up, dn;
+    int64_t dim = 0;
+    hub::DeviceTables dev;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = HUBBARD_FP64;
+    uint64_t seed = 12043425ull;
+};
+
+namespace hub {
+
+// builder.cpp
+void build_spin_table(int sites, const std::vector<int32_t> &edges, int n, SpinTable &out);
+uint64_t binomial(int n, int k);
+
+// tridiag.cpp: symmetric tridiagonal T with diagonal d[0..m-1] and
+// off-diagonal e[i] between rows i and i+1 (i < m-1).
+double tridiag_lowest(const double *d, const double *e, int m);
+void tridiag_lowest_vector(const double *d, const double *e, int m, double lam, double *y);
+
+// kernels.hip: launchers (all asynchronous on `s`).
+struct HvArgs {
+    const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
+    const uint16_t *nnz_up, *nnz_dn;
+    int64_t dim_up, dim_dn;
+    int32_t w_up, w_dn;
+    double t, U;
+};
+enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2 };
+enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2 };
+
+// HV_STORE:    y = H x
+// HV_LANCZOS:  y = alpha H x + beta y (in place), alpha = coef[0], beta = coef[1];
+//              partials[b] = block b's share of y.x
+// HV_RESIDUAL: nothing stored; partials[b] = share of |Hx - alpha x|^2,
+//              partials[nblocks + b] = share of x.Hx
+template <typename T>
+void launch_hv(const HvArgs &a, const T *x, T *y, int mode, double alpha, const double *coef, double *partials,
+               int nblocks, hipStream_t s);
+int hv_blocks(const HvArgs &a, int elem_bytes);
+
+template <typename T>
+void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);
+void launch_start_raw(uint64_t seed, double *f, int64_t n, hipStream_t s);
+void launch_start_norm2(const double *given, uint64_t seed, int64_t n, double *partials, int nblocks, hipStream_t s);
+template <typename T>
+void launch_start_fill(const double *given, uint64_t seed, double c, T *out, T *zero, int64_t n, hipStream_t s);
+template <typename T>
+void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int64_t n, bool first, hipStream_t s);
+void launch_psi_stats(const double *psi, const double *given, uint64_t seed, int64_t n, double *partials, int nblocks,
+                      hipStream_t s);
+void launch_scale(double *v, double c, int64_t n, hipStream_t s);
+void launch_reduce(const double *partials, int n, int stride, int count, double *out, hipStream_t s);
+void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s);
+void launch_init_scalars(double *S, hipStream_t s);
+int stream_blocks(int64_t n);
+
+}  // namespace hub

@@ -1,0 +1,458 @@
+// HIP kernels for gfx950 (CDNA4): the Hubbard H.v product and the vector
+// work of the Lanczos recurrence.
+//
+// H.v (Siro & Harju, Sec. 4.3).  The state vector x of dim = dim_up * dim_dn
+// elements (J order, eq. J-formula) is viewed as a row-major dim_up x dim_dn
+// matrix X: row r holds the amplitudes with up configuration r (the
+// "subvectors" of Fig. slots).  Then
+//     (H x)[r, d] = sum_k A_up[r, k] X[c_k(r), d]      (H_up (x) I: a combination of rows)
+//                 + sum_k A_dn[d, k] X[r, e_k(d)]      (I (x) H_dn: a gather inside row r)
+//                 + U popcount(up_r & dn_d) X[r, d]    (interaction, generated on the fly)
+// with every hopping element equal to -t * sgn (Sec. 2.1).  One workgroup
+// owns one row at a time: it stages X[r, :] in LDS (a row is at most 160 KB),
+// reads the row's up-hopping entries as wave-uniform scalars, and each lane
+// produces the outputs of its columns d.  The three terms run in one kernel,
+// as the paper prescribes, so x is read from HBM once for the gathers.
+//
+// Every reduction (the dot products of Alg. 1) is written as one FP64 partial
+// per workgroup and summed by a single workgroup in a fixed order, so a run is
+// bitwise reproducible and a replayed recurrence retraces the first pass.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hub {
+
+constexpr uint32_t kColMask = 0x7FFFFFFFu;
+
+__device__ inline double block_sum(double v, double *scratch)
+{
+    // wave64 shuffle tree, then one value per wave through LDS
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        scratch[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; w++)
+            s += scratch[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+struct HvParams {
+    const uint32_t *__restrict__ states_up;
+    const uint32_t *__restrict__ states_dn;
+    const uint32_t *__restrict__ up_rows;
+    const uint32_t *__restrict__ dn_cols;
+    const uint16_t *__restrict__ nnz_up;
+    const uint16_t *__restrict__ nnz_dn;
+    int64_t dim_up, dim_dn;
+    int32_t w_up, w_dn;
+    double t, U;
+};
+
+template <typename T, int MODE, bool STAGE>
+__global__ __launch_bounds__(1024) void hv_kernel(HvParams p, const T *__restrict__ x, T *__restrict__ y,
+                                                  double alpha, double beta, const double *__restrict__ coef,
+                                                  double *__restrict__ partials)
+{
+    if (MODE == HV_LANCZOS) {
+        alpha = coef[0];
+        beta = coef[1];
+    }
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    __shared__ double red[16];
+
+    const int64_t ddn = p.dim_dn;
+    const T tp = (T)p.t, tm = (T)(-p.t), U = (T)p.U;
+    const T a_s = (T)alpha, b_s = (T)beta;
+    double acc0 = 0.0, acc1 = 0.0;
+
+    for (int64_t r = blockIdx.x; r < p.dim_up; r += gridDim.x) {
+        const T *__restrict__ xr = x + r * ddn;
+        if (STAGE) {
+            for (int64_t d = threadIdx.x; d < ddn; d += blockDim.x)
+                xs[d] = xr[d];
+            __syncthreads();
+        }
+        const uint32_t su = p.states_up[r];
+        const int nu = p.nnz_up[r];
+        const uint32_t *__restrict__ urow = p.up_rows + r * p.w_up;
+        for (int64_t d = threadIdx.x; d < ddn; d += blockDim.x) {
+            const T xv = STAGE ? xs[d] : xr[d];
+            T h = U * (T)__popc(su & p.states_dn[d]) * xv;
+            const int nd = p.nnz_dn[d];
+            for (int k = 0; k < nd; k++) {
+                const uint32_t e = p.dn_cols[(int64_t)k * ddn + d];
+                const T v = STAGE ? xs[e & kColMask] : xr[e & kColMask];
+                h = fma((e >> 31) ? tp : tm, v, h);
+            }
+            for (int k = 0; k < nu; k++) {
+                const uint32_t e = urow[k];
+                const T v = x[(int64_t)(e & kColMask) * ddn + d];
+                h = fma((e >> 31) ? tp : tm, v, h);
+            }
+            const int64_t J = r * ddn + d;
+            if (MODE == HV_STORE) {
+                y[J] = h;
+            } else if (MODE == HV_LANCZOS) {
+                const T q = a_s * h + b_s * y[J];
+                y[J] = q;
+                acc0 += (double)q * (double)xv;
+            } else {
+                const double res = (double)h - alpha * (double)xv;
+                acc0 += res * res;
+                acc1 += (double)xv * (double)h;
+            }
+        }
+        if (STAGE)
+            __syncthreads();
+    }
+    if (MODE != HV_STORE) {
+        double s0 = block_sum(acc0, red);
+        if (threadIdx.x == 0)
+            partials[blockIdx.x] = s0;
+        if (MODE == HV_RESIDUAL) {
+            double s1 = block_sum(acc1, red);
+            if (threadIdx.x == 0)
+                partials[gridDim.x + blockIdx.x] = s1;
+        }
+    }
+}
+
+static HvParams to_params(const HvArgs &a)
+{
+    HvParams p;
+    p.states_up = a.states_up;
+    p.states_dn = a.states_dn;
+    p.up_rows = a.up_rows;
+    p.dn_cols = a.dn_cols;
+    p.nnz_up = a.nnz_up;
+    p.nnz_dn = a.nnz_dn;
+    p.dim_up = a.dim_up;
+    p.dim_dn = a.dim_dn;
+    p.w_up = a.w_up;
+    p.w_dn = a.w_dn;
+    p.t = a.t;
+    p.U = a.U;
+    return p;
+}
+
+static int hv_threads(int64_t dim_dn)
+{
+    int64_t t = ((dim_dn + 63) / 64) * 64;
+    return (int)(t < 1024 ? t : 1024);
+}
+
+// the row must fit in LDS beside the kernel's small static arrays
+static bool hv_stage(const HvArgs &a, int elem_bytes) { return a.dim_dn * elem_bytes <= 160 * 1024 - 512; }
+
+int hv_blocks(const HvArgs &a, int elem_bytes)
+{
+    // every workgroup resident at once: LDS bounds how many fit on a CU
+    const int64_t lds = hv_stage(a, elem_bytes) ? a.dim_dn * elem_bytes : 0;
+    const int threads = hv_threads(a.dim_dn);
+    int per_cu = 2048 / threads;
+    if (lds > 0) {
+        int by_lds = (int)((160 * 1024) / lds);
+        per_cu = by_lds < per_cu ? by_lds : per_cu;
+    }
+    if (per_cu < 1)
+        per_cu = 1;
+    int64_t n = (int64_t)256 * per_cu;
+    return (int)(a.dim_up < n ? a.dim_up : n);
+}
+
+template <typename T, int MODE>
+static void launch_hv_mode(const HvArgs &a, const T *x, T *y, double alpha, double beta, const double *coef,
+                           double *partials, int nblocks, hipStream_t s)
+{
+    const HvParams p = to_params(a);
+    const int threads = hv_threads(a.dim_dn);
+    if (hv_stage(a, sizeof(T))) {
+        const size_t lds = (size_t)a.dim_dn * sizeof(T);
+        auto k = hv_kernel<T, MODE, true>;
+        HUB_HIP(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k, dim3(nblocks), dim3(threads), lds, s, p, x, y, alpha, beta, coef, partials);
+    } else {
+        hipLaunchKernelGGL((hv_kernel<T, MODE, false>), dim3(nblocks), dim3(threads), 0, s, p, x, y, alpha, beta,
+                           coef, partials);
+    }
+    HUB_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_hv(const HvArgs &a, const T *x, T *y, int mode, double alpha, const double *coef, double *partials,
+               int nblocks, hipStream_t s)
+{
+    if (mode == HV_STORE)
+        launch_hv_mode<T, HV_STORE>(a, x, y, alpha, 0.0, coef, partials, nblocks, s);
+    else if (mode == HV_LANCZOS)
+        launch_hv_mode<T, HV_LANCZOS>(a, x, y, alpha, 0.0, coef, partials, nblocks, s);
+    else
+        launch_hv_mode<T, HV_RESIDUAL>(a, x, y, alpha, 0.0, coef, partials, nblocks, s);
+}
+
+template void launch_hv<double>(const HvArgs &, const double *, double *, int, double, const double *, double *,
+                                int, hipStream_t);
+template void launch_hv<float>(const HvArgs &, const float *, float *, int, double, const double *, double *, int,
+                               hipStream_t);
+
+// ------------------------------------------------------------ vector kernels
+
+int stream_blocks(int64_t n)
+{
+    int64_t b = (n + 2047) / 2048;
+    if (b > 2048)
+        b = 2048;
+    return (int)(b < 1 ? 1 : b);
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// q = q - c f with c from the device scalars; partial sums of q.q (Alg. 1:
+// q_j <- q_j - a_j f_j, then the norm that becomes b_{j+1}).
+template <typename T>
+__global__ __launch_bounds__(256) void axpy_norm_kernel(T *__restrict__ w, const T *__restrict__ v,
+                                                        const double *__restrict__ coef, int64_t n,
+                                                        double *__restrict__ partials)
+{
+    __shared__ double red[4];
+    const T cs = (T)coef[0];
+    double acc = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const T q = w[i] - cs * v[i];
+        w[i] = q;
+        acc += (double)q * (double)q;
+    }
+    double s = block_sum(acc, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = s;
+}
+
+template <typename T>
+void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(axpy_norm_kernel<T>, dim3(nblocks), dim3(256), 0, s, w, v, coef, n, partials);
+    HUB_HIP(hipGetLastError());
+}
+template void launch_axpy_norm<double>(double *, const double *, const double *, int64_t, double *, int,
+                                       hipStream_t);
+template void launch_axpy_norm<float>(float *, const float *, const double *, int64_t, double *, int, hipStream_t);
+
+// SplitMix64 (Steele, Lea & Flood 2014): output k of the stream started at
+// `seed` is the published finaliser applied to seed + k * 0x9E3779B97F4A7C15.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Element J of the random start vector: 2u - 1 with u = top 53 bits / 2^53.
+__device__ inline double start_value(uint64_t seed, int64_t J)
+{
+    const double u = (double)(splitmix64_at(seed, (uint64_t)J + 1) >> 11) * 0x1.0p-53;
+    return 2.0 * u - 1.0;
+}
+
+__device__ inline double start_or_given(const double *__restrict__ given, uint64_t seed, int64_t J)
+{
+    return given ? given[J] : start_value(seed, J);
+}
+
+__global__ __launch_bounds__(256) void start_raw_kernel(uint64_t seed, double *__restrict__ f, int64_t n)
+{
+    GRID_STRIDE(i, n) f[i] = start_value(seed, i);
+}
+
+void launch_start_raw(uint64_t seed, double *f, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(start_raw_kernel, dim3(stream_blocks(n)), dim3(256), 0, s, seed, f, n);
+    HUB_HIP(hipGetLastError());
+}
+
+// partial sums of f.f for the start vector (given, or generated from the seed)
+__global__ __launch_bounds__(256) void start_norm2_kernel(const double *__restrict__ given, uint64_t seed, int64_t n,
+                                                          double *__restrict__ partials)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double f = start_or_given(given, seed, i);
+        acc += f * f;
+    }
+    double s = block_sum(acc, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = s;
+}
+
+void launch_start_norm2(const double *given, uint64_t seed, int64_t n, double *partials, int nblocks,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(start_norm2_kernel, dim3(nblocks), dim3(256), 0, s, given, seed, n, partials);
+    HUB_HIP(hipGetLastError());
+}
+
+// out = (T)(c f), the normalised start vector f_1 in the working precision;
+// zero = the previous vector f_0 = 0 (Alg. 1), when not NULL.
+template <typename T>
+__global__ __launch_bounds__(256) void start_fill_kernel(const double *__restrict__ given, uint64_t seed, double c,
+                                                         T *__restrict__ out, T *__restrict__ zero, int64_t n)
+{
+    GRID_STRIDE(i, n)
+    {
+        out[i] = (T)(c * start_or_given(given, seed, i));
+        if (zero)
+            zero[i] = (T)0;
+    }
+}
+
+template <typename T>
+void launch_start_fill(const double *given, uint64_t seed, double c, T *out, T *zero, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(start_fill_kernel<T>, dim3(stream_blocks(n)), dim3(256), 0, s, given, seed, c, out, zero, n);
+    HUB_HIP(hipGetLastError());
+}
+template void launch_start_fill<double>(const double *, uint64_t, double, double *, double *, int64_t, hipStream_t);
+template void launch_start_fill<float>(const double *, uint64_t, double, float *, float *, int64_t, hipStream_t);
+
+// psi += y_j * (1/s) * v, where v holds s f_j and 1/s is the device scalar
+// coef[0] (the ground-state vector sum_j y_j f_j of the replayed recurrence).
+template <typename T>
+__global__ __launch_bounds__(256) void psi_acc_kernel(double *__restrict__ psi, const T *__restrict__ v, double yj,
+                                                      const double *__restrict__ coef, int64_t n, int first)
+{
+    const double c = yj * coef[0];
+    GRID_STRIDE(i, n)
+    {
+        const double add = c * (double)v[i];
+        psi[i] = first ? add : psi[i] + add;
+    }
+}
+
+template <typename T>
+void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int64_t n, bool first, hipStream_t s)
+{
+    hipLaunchKernelGGL(psi_acc_kernel<T>, dim3(stream_blocks(n)), dim3(256), 0, s, psi, v, yj, coef, n,
+                       first ? 1 : 0);
+    HUB_HIP(hipGetLastError());
+}
+template void launch_psi_acc<double>(double *, const double *, double, const double *, int64_t, bool, hipStream_t);
+template void launch_psi_acc<float>(double *, const float *, double, const double *, int64_t, bool, hipStream_t);
+
+// partial sums of psi.psi and psi.f1
+__global__ __launch_bounds__(256) void psi_stats_kernel(const double *__restrict__ psi, const double *__restrict__ given,
+                                                        uint64_t seed, int64_t n, double *__restrict__ partials)
+{
+    __shared__ double red[4];
+    double a0 = 0.0, a1 = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double v = psi[i];
+        a0 += v * v;
+        a1 += v * start_or_given(given, seed, i);
+    }
+    double s0 = block_sum(a0, red);
+    double s1 = block_sum(a1, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = s0;
+        partials[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+void launch_psi_stats(const double *psi, const double *given, uint64_t seed, int64_t n, double *partials, int nblocks,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(psi_stats_kernel, dim3(nblocks), dim3(256), 0, s, psi, given, seed, n, partials);
+    HUB_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(double *__restrict__ v, double c, int64_t n)
+{
+    GRID_STRIDE(i, n) v[i] *= c;
+}
+
+void launch_scale(double *v, double c, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(scale_kernel, dim3(stream_blocks(n)), dim3(256), 0, s, v, c, n);
+    HUB_HIP(hipGetLastError());
+}
+
+// Fixed-order sum of `n` partials (block k sums partials[k*stride ...]).
+// mode RED_PLAIN: out[k] = sum.
+// mode RED_DOT (after the H.v step of iteration j): a_j = sum * S[0];
+//   S[3] = a_j * S[0] (the coefficient of the q - a_j f_j update); hist[2j] = a_j.
+// mode RED_NORM (after that update): b_{j+1} = sqrt(sum); hist[2j+1] = b_{j+1};
+//   the roles of the two vectors swap, so the next H.v gets
+//   alpha = 1/b_{j+1}, beta = -b_{j+1} * S[0] (old 1/s), and S[0] = 1/b_{j+1}.
+// S = device scalars {1/s of the current vector, alpha, beta, c}.
+__global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__ partials, int n, int stride,
+                                                      double *__restrict__ out, int mode, double *__restrict__ S,
+                                                      double *__restrict__ hist, int j)
+{
+    __shared__ double red[16];
+    const double *src = partials + (int64_t)blockIdx.x * stride;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        acc += src[i];
+    double s = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        if (mode == RED_PLAIN) {
+            out[blockIdx.x] = s;
+        } else if (mode == RED_DOT) {
+            const double a = s * S[0];
+            S[3] = a * S[0];
+            hist[2 * j] = a;
+        } else {
+            const double b = sqrt(s);
+            hist[2 * j + 1] = b;
+            S[2] = -b * S[0];
+            S[0] = b > 0.0 ? 1.0 / b : 0.0;
+            S[1] = S[0];
+        }
+    }
+}
+
+void launch_reduce(const double *partials, int n, int stride, int count, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(count), dim3(1024), 0, s, partials, n, stride, out, (int)RED_PLAIN,
+                       (double *)nullptr, (double *)nullptr, 0);
+    HUB_HIP(hipGetLastError());
+}
+
+void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, partials, n, 0, (double *)nullptr, mode, S, hist, j);
+    HUB_HIP(hipGetLastError());
+}
+
+// S = {1, 1, 0, 0}: f_1 has scale 1 and b_1 = 0 (Alg. 1).
+__global__ void init_scalars_kernel(double *S)
+{
+    if (threadIdx.x == 0) {
+        S[0] = 1.0;
+        S[1] = 1.0;
+        S[2] = 0.0;
+        S[3] = 0.0;
+    }
+}
+
+void launch_init_scalars(double *S, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, S);
+    HUB_HIP(hipGetLastError());
+}
+
+}  // namespace hub

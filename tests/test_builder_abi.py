@@ -1,0 +1,157 @@
+"""Host-side checks of the GPU library (CPU only): the C ABI loads and exports
+every declared symbol, the basis and ELL hopping tables are bit-exact against
+the oracle, and argument validation returns the documented codes."""
+import ctypes
+import math
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from conftest import golden_rows
+
+hb = pytest.importorskip("paper_1204_3425_amd")
+
+
+def ell_pack_column_major(rows, width):
+    """Test-side ELL packer (Sec. 4.2, Fig. ELL): each row's (col, value) pairs in
+    order, padded to `width` with (pad_col, pad_val), flattened column-major."""
+    n = len(rows)
+    cols = np.zeros((width, n), dtype=np.int64)
+    vals = np.zeros((width, n), dtype=np.float64)
+    for r, row in enumerate(rows):
+        for k, (c, v) in enumerate(row):
+            cols[k, r] = c
+            vals[k, r] = v
+    return cols.reshape(-1), vals.reshape(-1)
+
+
+def test_ell_packer_reproduces_figure():
+    """The test packer gives Fig. ELL's column-major data and index vectors."""
+    lines = golden_rows("ell_example.txt")
+    i_m, i_d, i_x = [k for k, ln in enumerate(lines) if ln[0] in ("matrix", "data", "indices")]
+    A = np.array([[float(v) for v in ln] for ln in lines[i_m + 1:i_d]])
+    rows = [[(c, A[r, c]) for c in range(A.shape[1]) if A[r, c] != 0] for r in range(A.shape[0])]
+    w = max(len(r) for r in rows)
+    cols, vals = ell_pack_column_major(rows, w)
+    want_d = lines[i_d + 1]
+    want_i = lines[i_x + 1]
+    assert len(want_d) == len(vals) == len(want_i)
+    for k in range(len(vals)):
+        if want_d[k] == "*":
+            assert vals[k] == 0 and cols[k] == 0  # padding set to zero
+        else:
+            assert vals[k] == float(want_d[k]) and cols[k] == int(want_i[k])
+
+
+def test_every_declared_symbol_is_exported():
+    text = open(hb.HEADER_PATH).read()
+    names = sorted(set(re.findall(r"\b(hubbard_[a-z_0-9]+)\s*\(", text)))
+    assert "hubbard_build" in names and "hubbard_lanczos" in names and "hubbard_apply" in names
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+CASES = [
+    (4, workload.ring(4), 2, 3),
+    (6, workload.torus(2, 3), 3, 2),
+    (8, workload.ring(8), 4, 4),
+    (10, workload.ring(10), 3, 5),
+    (12, workload.torus(3, 4), 6, 5),
+    (12, workload.torus(4, 3), 4, 8),
+    (14, workload.ring(14), 7, 7),
+    (16, workload.torus(4, 4), 8, 8),
+    (16, workload.torus(4, 4), 5, 3),
+    (9, workload.chain(9), 0, 9),
+]
+
+
+@pytest.mark.parametrize("ns,edges,nu,nd", CASES)
+def test_basis_and_tables_bit_exact(ns, edges, nu, nd):
+    """Basis words and signed ELL tables equal the oracle's (Sec. 2.1, Sec. 4.2)."""
+    h = hb.hubbard_build(ns, edges, nu, nd, 1.0, 4.0)
+    m = oracle.Model(ns, edges, nu, nd, 1.0, 4.0)
+    info = hb.hubbard_info(h)
+    assert info["dim"] == m.dim == math.comb(ns, nu) * math.comb(ns, nd)
+    for spin in (0, 1):
+        states, rs, col, val = m.table(spin)
+        assert np.array_equal(hb.hubbard_export_basis(h, spin), states)
+        d = len(states)
+        width = int(np.diff(rs).max()) if d else 0
+        assert info["w_up" if spin == 0 else "w_dn"] == width
+        assert info["nnz_up" if spin == 0 else "nnz_dn"] == len(col)
+        # oracle values are -t * sgn with t = 1
+        rows = [[(int(col[k]), -val[k]) for k in range(rs[r], rs[r + 1])] for r in range(d)]
+        want_col, want_sgn = ell_pack_column_major(rows, width)
+        got_col, got_sgn = hb.hubbard_export_table(h, spin)
+        assert np.array_equal(got_col, want_col)
+        assert np.array_equal(got_sgn.astype(np.float64), want_sgn)
+
+
+def test_table1_through_export():
+    """Sec. 2.1, Table 1, read through the library's exported basis."""
+    h = hb.hubbard_build(4, workload.ring(4), 2, 3, 1.0, 0.0)
+    up, dn = list(hb.hubbard_export_basis(h, 0)), list(hb.hubbard_export_basis(h, 1))
+    for u, d, iu, idn, J in golden_rows("table1_labels.txt"):
+        assert up.index(int(u, 2)) == int(iu) and dn.index(int(d, 2)) == int(idn)
+        assert int(iu) * h.dim_dn + int(idn) == int(J)
+
+
+@pytest.mark.parametrize("ns,edges,n,width", [(8, workload.ring(8), 4, 8), (14, workload.ring(14), 7, 14),
+                                              (16, workload.torus(4, 4), 8, 32)])
+def test_widths_and_nnz_closed_form(ns, edges, n, width):
+    info = hb.hubbard_info(hb.hubbard_build(ns, edges, n, n, 1.0, 1.0))
+    assert info["w_up"] == info["w_dn"] == width
+    assert info["nnz_up"] == 2 * len(edges) * math.comb(ns - 2, n - 1)
+
+
+@pytest.mark.parametrize("args", [
+    (0, [], 0, 0), (33, [], 1, 1), (4, [(0, 4)], 1, 1), (4, [(1, 1)], 1, 1), (4, [(0, 1), (1, 0)], 1, 1),
+    (4, [(0, 1)], 5, 1), (4, [(0, 1)], 1, -1), (4, [(-1, 2)], 1, 1)])
+def test_invalid_build_arguments(args):
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_build(*args, t=1.0, U=1.0)
+    assert ei.value.code == hb.HUBBARD_EINVAL
+
+
+@pytest.mark.parametrize("t,U", [(float("nan"), 1.0), (1.0, float("inf"))])
+def test_non_finite_parameters(t, U):
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_build(4, workload.ring(4), 2, 2, t, U)
+    assert ei.value.code == hb.HUBBARD_EINVAL
+
+
+def test_range_error():
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_build(32, workload.ring(32), 16, 16, 1.0, 1.0)
+    assert ei.value.code == hb.HUBBARD_ERANGE
+
+
+def test_null_arguments_rejected():
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    lib.hubbard_build.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    assert lib.hubbard_build(4, None, 0, 1, 1, 1.0, 1.0, None) == hb.HUBBARD_EINVAL
+    assert lib.hubbard_build(4, None, 2, 1, 1, 1.0, 1.0, None) == hb.HUBBARD_EINVAL
+    lib.hubbard_info.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.hubbard_info(None, None) == hb.HUBBARD_EINVAL
+    lib.hubbard_free.argtypes = [ctypes.c_void_p]
+    assert lib.hubbard_free(None) == hb.HUBBARD_OK
+
+
+def test_strerror_and_last_error():
+    assert hb.hubbard_strerror(hb.HUBBARD_EINVAL) == "invalid argument"
+    with pytest.raises(hb.HubbardError):
+        hb.hubbard_build(4, [(0, 0)], 1, 1)
+    assert "distinct" in hb.hubbard_last_error()
+
+
+def test_precision_and_seed_setters():
+    h = hb.hubbard_build(4, workload.ring(4), 2, 2)
+    hb.hubbard_set_precision(h, hb.HUBBARD_MIXED)
+    hb.hubbard_set_seed(h, 5)
+    with pytest.raises(hb.HubbardError):
+        hb.hubbard_set_precision(h, 7)

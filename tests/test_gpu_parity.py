@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (derived from the arithmetic; the method itself fixes E0 to 1e-10
+relative in FP64 and 1e-6 in mixed precision):
+  * FP64 H.v: every output is a sum of at most 1 + w_up + w_dn terms of size
+    <= max(|U| * Ns, |t|) * max|x|; summed in a different order its error is
+    below ~40 ulp of that scale, so max|y - y_ref| <= 1e-13 * max|y_ref| holds
+    with a wide margin.
+  * FP32 H.v (FP32 accumulation of FP32 inputs): per element
+    |err| <= n u sum|terms| with u = 2^-24 and n <= 1 + w_up + w_dn; checked
+    element-wise against that bound and norm-wise at 1e-5.
+  * Lanczos: a_j, b_{j+1} agree with the oracle's from the same start vector
+    while rounding has not yet been amplified (first 20 steps, 1e-12 relative;
+    Sec. 5 reports this same check), and E0 within 1e-10 relative (FP64) or
+    1e-6 (mixed).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+
+torch = pytest.importorskip("torch")
+hb = pytest.importorskip("paper_1204_3425_amd")
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _build(p):
+    return hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+
+
+def _oracle(p):
+    return oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+
+
+def _apply_gpu(h, x_np, precision):
+    hb.hubbard_set_precision(h, precision)
+    dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
+    x = torch.from_numpy(x_np).to(DEV, dt)
+    y = torch.empty_like(x)
+    hb.hubbard_apply(h, x, y)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def _term_bound(p, info):
+    return max(abs(p.U) * p.sites, abs(p.t)) * (1 + info["w_up"] + info["w_dn"])
+
+
+APPLY_CASES = [
+    workload.problem("ring8", 8, workload.ring(8), 4, 4, 1.0, 4.0),
+    workload.problem("ring7_ragged", 7, workload.ring(7), 3, 2, 0.7, 2.5),
+    workload.problem("torus3x4", 12, workload.torus(3, 4), 5, 6, 1.0, 8.0),
+    workload.problem("ring10_U0", 10, workload.ring(10), 4, 5, 1.3, 0.0),
+    workload.problem("ring10_t0", 10, workload.ring(10), 5, 5, 0.0, 3.0),
+    workload.problem("dn_empty", 9, workload.ring(9), 4, 0, 1.0, 2.0),
+    workload.problem("up_empty", 9, workload.ring(9), 0, 4, 1.0, 2.0),
+    workload.problem("single_state", 5, workload.ring(5), 5, 0, 1.0, 2.0),
+    workload.problem("chain11", 11, workload.chain(11), 5, 6, 1.0, 5.0),
+    # dim_dn * 8 bytes > 160 KB: the down-spin rows do not fit in LDS
+    workload.problem("ring18_wide_rows", 18, workload.ring(18), 1, 9, 1.0, 4.0),
+    workload.problem("ring14", 14, workload.ring(14), 7, 7, 1.0, 4.0),
+]
+
+
+@pytest.mark.parametrize("p", APPLY_CASES, ids=[c.name for c in APPLY_CASES])
+@pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
+def test_apply_matches_oracle(p, precision):
+    _say("apply", p.name, "dim", p.dim, "precision", precision)
+    h = _build(p)
+    m = _oracle(p)
+    x = workload.random_vector(p.dim, p.seed + 1)
+    if precision == hb.HUBBARD_MIXED:
+        x = x.astype(np.float32).astype(np.float64)
+    ref = m.apply(x)
+    got = _apply_gpu(h, x, precision)
+    scale = max(1.0, np.abs(ref).max())
+    if precision == hb.HUBBARD_FP64:
+        assert np.abs(got - ref).max() <= 1e-13 * scale
+    else:
+        info = hb.hubbard_info(h)
+        bound = (1 + info["w_up"] + info["w_dn"]) * 2.0**-24 * _term_bound(p, info) * np.abs(x).max()
+        assert np.abs(got - ref).max() <= bound
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref) + 1e-30
+
+
+@pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
+def test_apply_4x4_sampled_rows(precision):
+    """The 4x4 half-filled sector (dim 165,636,900) at full size, in the launch
+    configuration the benchmark uses: outputs checked on 3000 sampled rows
+    (including the first and last row and the last column)."""
+    p = workload.square4x4()
+    _say("apply 4x4 sampled, precision", precision)
+    h = _build(p)
+    m = _oracle(p)
+    x = workload.random_vector(p.dim, p.seed + 2)
+    if precision == hb.HUBBARD_MIXED:
+        x = x.astype(np.float32).astype(np.float64)
+    got = _apply_gpu(h, x, precision)
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([[0, p.dim - 1, p.dim_dn - 1, p.dim - p.dim_dn], rng.integers(0, p.dim, 3000)])
+    ref = m.apply_rows(x, rows)
+    g = got[rows]
+    if precision == hb.HUBBARD_FP64:
+        assert np.abs(g - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    else:
+        info = hb.hubbard_info(h)
+        bound = (1 + info["w_up"] + info["w_dn"]) * 2.0**-24 * _term_bound(p, info)
+        assert np.abs(g - ref).max() <= bound
+        assert np.linalg.norm(g - ref) <= 1e-5 * np.linalg.norm(ref)
+    # symmetry of H at full size: <u, H v> == <H u, v>
+    u = workload.random_vector(p.dim, p.seed + 3)
+    if precision == hb.HUBBARD_MIXED:
+        u = u.astype(np.float32).astype(np.float64)
+    Hu = _apply_gpu(h, u, precision)
+    lhs, rhs = float(u @ got), float(Hu @ x)
+    tol = 1e-11 if precision == hb.HUBBARD_FP64 else 1e-4
+    assert abs(lhs - rhs) <= tol * (np.abs(u).sum() + np.abs(x).sum())
+
+
+def test_apply_rejects_overlap_and_bad_tensors():
+    p = workload.ring8()
+    h = _build(p)
+    x = torch.zeros(p.dim * 2, dtype=torch.float64, device=DEV)
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_apply(h, x.data_ptr(), x.data_ptr() + 8 * 100)
+    assert ei.value.code == hb.HUBBARD_EINVAL
+    with pytest.raises(TypeError):
+        hb.hubbard_apply(h, torch.zeros(p.dim, device=DEV), torch.zeros(p.dim, device=DEV))
+    with pytest.raises(ValueError):
+        hb.hubbard_apply(h, torch.zeros(p.dim + 1, dtype=torch.float64, device=DEV),
+                         torch.zeros(p.dim, dtype=torch.float64, device=DEV))
+
+
+def test_start_vector_bit_exact():
+    """The device SplitMix64 start vector equals the oracle's bit for bit."""
+    for seed, dim in [(0, 1000), (workload.BASE_SEED, 123457), (2**63 + 11, 4900)]:
+        f = torch.empty(dim, dtype=torch.float64, device=DEV)
+        hb.hubbard_start_raw(seed, dim, f)
+        torch.cuda.synchronize()
+        assert np.array_equal(f.cpu().numpy(), oracle.start_vector(seed, dim, normalise=False))
+
+
+def _lanczos_gpu(h, p, precision, tol, max_iter, want_psi=False, start=None):
+    psi = torch.empty(p.dim, dtype=torch.float64, device=DEV) if want_psi else None
+    r = hb.hubbard_lanczos_ex(h, tol=tol, max_iter=max_iter, precision=precision, seed=p.seed, psi=psi,
+                              start=start)
+    torch.cuda.synchronize()
+    if want_psi:
+        r["psi"] = psi.cpu().numpy()
+    return r
+
+
+def test_lanczos_ring8_fp64_matches_oracle():
+    p = workload.ring8()
+    _say("lanczos ring8 fp64")
+    h = _build(p)
+    m = _oracle(p)
+    ref = m.lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300, want_psi=True)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 300, want_psi=True)
+    assert got["E0"] == pytest.approx(ref["E0"], rel=1e-10)
+    k = 20
+    assert np.allclose(got["a"][:k], ref["a"][:k], rtol=1e-12, atol=1e-13)
+    assert np.allclose(got["b"][:k], ref["b"][:k], rtol=1e-12, atol=1e-13)
+    assert got["stop"] == "converged"
+    assert abs(np.linalg.norm(got["psi"]) - 1) < 1e-12
+    assert abs(got["psi"] @ ref["psi"]) > 1 - 1e-8
+    assert got["residual"] < 1e-5 and got["residual"] == pytest.approx(
+        np.linalg.norm(m.apply(got["psi"]) - got["E0"] * got["psi"]), rel=1e-6, abs=1e-12)
+    assert got["rayleigh"] == pytest.approx(ref["E0"], rel=1e-11)
+
+
+def test_lanczos_ring8_plain_entry_point():
+    p = workload.ring8()
+    h = _build(p)
+    hb.hubbard_set_seed(h, p.seed)
+    rc, e0 = hb.hubbard_lanczos(h, 1e-12, 300)
+    assert rc == hb.HUBBARD_OK
+    ref = _oracle(p).lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300)["E0"]
+    assert e0 == pytest.approx(ref, rel=1e-10)
+    rc, _ = hb.hubbard_lanczos(h, 1e-14, 3)
+    assert rc == hb.HUBBARD_ENOCONV
+
+
+def test_lanczos_given_start_vector():
+    p = workload.problem("torus2x4", 8, workload.torus(2, 4), 3, 4, 1.0, 6.0)
+    h = _build(p)
+    m = _oracle(p)
+    f = workload.random_vector(p.dim, 77)
+    f /= np.linalg.norm(f)
+    ref = m.lanczos(f, tol=1e-12, max_iter=200)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 200, start=torch.from_numpy(f).to(DEV))
+    assert np.allclose(got["a"][:15], ref["a"][:15], rtol=1e-12, atol=1e-13)
+    assert got["E0"] == pytest.approx(ref["E0"], rel=1e-10)
+
+
+def test_lanczos_ring14_against_golden():
+    """14-site ring, FP64 and mixed, against the stored oracle run (same seed)."""
+    g = json.load(open(os.path.join(GOLDEN, "oracle_ring14.json")))
+    p = workload.ring14()
+    assert g["problem"]["dim"] == p.dim and g["problem"]["seed"] == p.seed
+    h = _build(p)
+    _say("lanczos ring14 fp64")
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 400, want_psi=True)
+    assert got["E0"] == pytest.approx(g["E0"], rel=1e-10)
+    assert np.allclose(got["a"][:20], g["a"][:20], rtol=1e-12, atol=1e-13)
+    assert np.allclose(got["b"][:20], g["b"][:20], rtol=1e-12, atol=1e-13)
+    assert got["residual"] < 1e-4
+    _say("lanczos ring14 mixed")
+    mix = _lanczos_gpu(h, p, hb.HUBBARD_MIXED, 1e-10, 400, want_psi=True)
+    assert mix["E0"] == pytest.approx(g["E0"], rel=1e-6)
+    assert mix["rayleigh"] == pytest.approx(g["E0"], rel=1e-6)
+    assert mix["residual"] < 1e-2
+
+
+def test_lanczos_4x4_against_golden():
+    path = os.path.join(GOLDEN, "oracle_square4x4.json")
+    if not os.path.exists(path):
+        pytest.skip("4x4 oracle run not stored")
+    g = json.load(open(path))
+    p = workload.square4x4()
+    h = _build(p)
+    n = g["max_iter"]
+    _say("lanczos 4x4 fp64", n)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, -1.0, n)
+    assert got["n_iter"] == g["n_iter"]
+    assert np.allclose(got["a"][:20], g["a"][:20], rtol=1e-12, atol=1e-13)
+    assert np.allclose(got["b"][:20], g["b"][:20], rtol=1e-12, atol=1e-13)
+    assert got["E0"] == pytest.approx(g["E0"], rel=1e-10)
+    _say("lanczos 4x4 mixed", n)
+    mix = _lanczos_gpu(h, p, hb.HUBBARD_MIXED, -1.0, n)
+    assert mix["E0"] == pytest.approx(g["E0"], rel=1e-6)
+
+
+def test_lanczos_is_deterministic():
+    p = workload.problem("torus3x4", 12, workload.torus(3, 4), 4, 5, 1.0, 6.0)
+    h = _build(p)
+    r1 = _lanczos_gpu(h, p, hb.HUBBARD_MIXED, -1.0, 60)
+    r2 = _lanczos_gpu(h, p, hb.HUBBARD_MIXED, -1.0, 60)
+    assert np.array_equal(r1["a"], r2["a"]) and np.array_equal(r1["b"], r2["b"])
+
+
+@pytest.mark.parametrize("p", [
+    workload.problem("one_state", 4, workload.ring(4), 4, 0, 1.0, 2.0),
+    workload.problem("dimer", 2, [(0, 1)], 1, 1, 1.0, 4.0),
+    workload.problem("tiny3", 3, workload.ring(3), 1, 1, 1.0, 1.0),
+], ids=lambda p: p.name)
+def test_lanczos_degenerate_sectors(p):
+    """dim 1 (breakdown at once), the dimer closed form, a 9-state sector that
+    exhausts its Krylov space."""
+    h = _build(p)
+    m = _oracle(p)
+    ref = m.lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=50, want_psi=True)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 50, want_psi=True)
+    assert got["E0"] == pytest.approx(ref["E0"], rel=1e-10, abs=1e-12)
+    assert got["n_iter"] == ref["n_iter"]
+    assert got["residual"] < 1e-6
+    if p.name == "dimer":
+        assert got["E0"] == pytest.approx(2 - math.sqrt(4 + 4), rel=1e-12)
+
+
+def test_batch_equals_alone():
+    probs = workload.batch64(6)
+    hs = [_build(p) for p in probs]
+    alone = [_lanczos_gpu(h, p, hb.HUBBARD_MIXED, 1e-10, 300) for h, p in zip(hs, probs)]
+    batch = hb.hubbard_lanczos_batch(hs, tol=1e-10, max_iter=300, precision=hb.HUBBARD_MIXED,
+                                     seeds=[p.seed for p in probs], history=True)
+    for a, b, p in zip(alone, batch, probs):
+        assert b["E0"] == pytest.approx(a["E0"], rel=1e-12), p.name
+        m = _oracle(p)
+        ref = m.lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300)
+        assert b["E0"] == pytest.approx(ref["E0"], rel=1e-6), p.name
