@@ -95,7 +95,8 @@ struct PinnedBuf {
 static void free_device(hubbard *h)
 {
     DeviceTables &d = h->dev;
-    void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn};
+    void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
+                    d.dn_groups64, d.dn_groups32, d.dn_nq};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -137,6 +138,29 @@ static void upload_tables(hubbard *h)
     d.dn_cols = upload<uint32_t>(cols.data(), cols.size() * 4, total);
     d.nnz_up = upload<uint16_t>(h->up.row_nnz.data(), h->up.row_nnz.size() * 2, total);
     d.nnz_dn = upload<uint16_t>(h->dn.row_nnz.data(), h->dn.row_nnz.size() * 2, total);
+    // row-pass groups: entry k of column d at ((k/4) * dim_dn + d) * 4 + k%4
+    const int64_t ddn = h->dn.dim;
+    const int ng = (h->dn.width + 3) / 4;
+    d.dn_ngroups = ng;
+    std::vector<uint8_t> nq((size_t)((ddn + 63) / 64), 0);
+    for (int64_t r = 0; r < ddn; r++) {
+        int need = (h->dn.row_nnz[(size_t)r] + 3) / 4;
+        uint8_t &slot = nq[(size_t)(r / 64)];
+        slot = (uint8_t)std::max<int>(slot, need);
+    }
+    for (int es : {8, 4}) {
+        std::vector<uint32_t> g((size_t)std::max(ng, 1) * (size_t)ddn * 4, (uint32_t)(ddn * es));
+        for (int64_t r = 0; r < ddn; r++)
+            for (int k = 0; k < h->dn.row_nnz[(size_t)r]; k++) {
+                size_t src = (size_t)k * (size_t)ddn + (size_t)r;
+                uint32_t off = (uint32_t)h->dn.col[src] * (uint32_t)es;
+                g[((size_t)(k / 4) * (size_t)ddn + (size_t)r) * 4 + (size_t)(k % 4)] =
+                    off | (h->dn.sgn[src] < 0 ? 0x80000000u : 0u);
+            }
+        uint32_t *dev = upload<uint32_t>(g.data(), g.size() * 4, total);
+        (es == 8 ? d.dn_groups64 : d.dn_groups32) = dev;
+    }
+    d.dn_nq = upload<uint8_t>(nq.data(), nq.size(), total);
     d.bytes = total;
 }
 
@@ -149,6 +173,10 @@ static HvArgs hv_args(const hubbard *h)
     a.dn_cols = h->dev.dn_cols;
     a.nnz_up = h->dev.nnz_up;
     a.nnz_dn = h->dev.nnz_dn;
+    a.dn_groups64 = reinterpret_cast<const uint4 *>(h->dev.dn_groups64);
+    a.dn_groups32 = reinterpret_cast<const uint4 *>(h->dev.dn_groups32);
+    a.dn_nq = h->dev.dn_nq;
+    a.dn_ngroups = h->dev.dn_ngroups;
     a.dim_up = h->up.dim;
     a.dim_dn = h->dn.dim;
     a.w_up = h->up.width;
@@ -187,12 +215,19 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     const int64_t n = h->dim;
     const HvArgs args = hv_args(h);
     hipStream_t s = h->stream;
-    const int hb = hv_blocks(args, sizeof(T));
-    const int sb = stream_blocks(n);
+    const HvPlan plan = make_hv_plan(args, sizeof(T));
+    const HvPlan plan64 = make_hv_plan(args, sizeof(double));
+    const int64_t ld = plan.ld;                 // padded row stride of the two work vectors
+    const int64_t npad = h->up.dim * ld;
+    const int hb = plan.nparts;
+    const int sb = stream_blocks(npad);
     const int max_iter = o.max_iter;
 
-    DevBuf vecA(sizeof(T) * (size_t)n), vecB(sizeof(T) * (size_t)n);
-    DevBuf partials(sizeof(double) * (size_t)(2 * std::max(hb, sb) + 64));
+    // one allocation for both work vectors; after the replay it is reused as
+    // the FP64 scratch of the residual (2 * npad * sizeof(T) >= npad * 8 bytes)
+    DevBuf work(2 * sizeof(T) * (size_t)npad);
+    T *vecs[2] = {work.as<T>(), work.as<T>() + npad};
+    DevBuf partials(sizeof(double) * (size_t)(2 * std::max(std::max(hb, plan64.nparts), sb) + 64));
     DevBuf scal(sizeof(double) * 8 + sizeof(double) * 2 * (size_t)(max_iter + 1));
     double *S = scal.as<double>();
     double *hist = S + 8;
@@ -211,13 +246,13 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     const double inv_norm = 1.0 / std::sqrt(hh[0]);
 
     auto start_pass = [&](T *C, T *P) {
-        launch_start_fill<T>(given, seed, inv_norm, C, P, n, s);
+        launch_start_fill<T>(given, seed, inv_norm, C, P, h->up.dim, h->dn.dim, ld, s);
         launch_init_scalars(S, s);
     };
     auto step = [&](T *C, T *P, int j0) {
-        launch_hv<T>(args, C, P, HV_LANCZOS, 0.0, S + 1, partials.as<double>(), hb, s);
+        launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, HV_LANCZOS, 0.0, S + 1, partials.as<double>(), s);
         launch_reduce_step(partials.as<double>(), hb, RED_DOT, S, hist, j0, s);
-        launch_axpy_norm<T>(P, C, S + 3, n, partials.as<double>(), sb, s);
+        launch_axpy_norm<T>(P, C, S + 3, npad, partials.as<double>(), sb, s);
         launch_reduce_step(partials.as<double>(), sb, RED_NORM, S, hist, j0, s);
     };
 
@@ -236,7 +271,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
         }
     } evguard{ev};
 
-    T *bufs[2] = {vecA.as<T>(), vecB.as<T>()};
+    T *bufs[2] = {vecs[0], vecs[1]};
     auto t0 = std::chrono::steady_clock::now();
     start_pass(bufs[0], bufs[1]);
     out.a.clear();
@@ -306,7 +341,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     start_pass(bufs[0], bufs[1]);
     for (int j0 = 0; j0 < m; j0++) {
         T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
-        launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, n, j0 == 0, s);
+        launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, h->up.dim, h->dn.dim, ld, j0 == 0, s);
         if (j0 + 1 < m)
             step(C, P, j0);
     }
@@ -320,8 +355,9 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
         c = -c;
     launch_scale(o.psi, c, n, s);
     // FP64 residual |H psi - E0 psi| and Rayleigh quotient <psi|H|psi>
-    const int hb64 = hv_blocks(args, sizeof(double));
-    launch_hv<double>(args, o.psi, nullptr, HV_RESIDUAL, out.e0, nullptr, partials.as<double>(), hb64, s);
+    const int hb64 = plan64.nparts;
+    launch_hv2<double>(args, plan64, o.psi, h->dn.dim, nullptr, 0, work.as<double>(), ld, HV_RESIDUAL, out.e0, nullptr,
+                       partials.as<double>(), s);
     launch_reduce(partials.as<double>(), hb64, hb64, 2, S + 4, s);
     HUB_HIP(hipMemcpyAsync(hh, S + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HUB_HIP(hipStreamSynchronize(s));
@@ -499,12 +535,13 @@ int hubbard_apply(hubbard_h h, const void *x, void *y)
             fail(HUBBARD_EINVAL, "x and y overlap");
         use_device(h);
         const HvArgs a = hv_args(h);
+        const int64_t ddn = h->dn.dim;
         if (h->precision == HUBBARD_FP64)
-            launch_hv<double>(a, static_cast<const double *>(x), static_cast<double *>(y), HV_STORE, 0.0, nullptr,
-                              nullptr, hv_blocks(a, 8), h->stream);
+            launch_hv2<double>(a, make_hv_plan(a, 8), static_cast<const double *>(x), ddn, static_cast<double *>(y), ddn,
+                               nullptr, 0, HV_STORE, 0.0, nullptr, nullptr, h->stream);
         else
-            launch_hv<float>(a, static_cast<const float *>(x), static_cast<float *>(y), HV_STORE, 0.0, nullptr,
-                             nullptr, hv_blocks(a, 4), h->stream);
+            launch_hv2<float>(a, make_hv_plan(a, 4), static_cast<const float *>(x), ddn, static_cast<float *>(y), ddn,
+                              nullptr, 0, HV_STORE, 0.0, nullptr, nullptr, h->stream);
         return HUBBARD_OK;
     });
 }

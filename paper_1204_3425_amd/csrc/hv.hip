@@ -1,0 +1,394 @@
+// Two-pass H.v for gfx950 (CDNA4).
+//
+// With the state vector viewed as the dim_up x dim_dn matrix X (Siro &
+// Harju, Sec. 4.3, Fig. slots; J = i_up * dim_dn + i_dn),
+//     H x = X A_dn^T + U D o X   +   A_up X.
+// The two hopping terms want different data movement, so each gets a pass of
+// its own:
+//
+// Row pass (I (x) H_dn and the interaction).  A workgroup stages whole rows of
+// X in LDS (RPB rows at once, each followed by a zero slot) and every lane
+// produces the outputs of its columns d by gathering X[r, e_k(d)] from LDS.
+// The down table is stored as groups of four 32-bit entries per column d
+// (byte offset of the source element in the staged row, sign in bit 31), and
+// all groups of a column are loaded before the first gather so the table
+// latency is paid once.  Padding entries point at the zero slot, so no lane
+// tests how many entries it owns; the sign of the hop is applied by flipping
+// the sign bit of the gathered value.  The group count is the maximum over the
+// 64 columns of a wave.
+//
+// Slab pass (H_up (x) I).  Output row r is a signed sum of whole rows
+// X[c_k(r), :].  Each XCD of the MI355X (workgroup i runs on XCD i mod 8)
+// sweeps its own 64-column slabs, so the slab of X that the row combinations
+// re-read stays in that XCD's 4 MB L2 while every CU of the XCD works on it.
+// A workgroup owns a fixed block of rows and keeps their up-hopping entries
+// in LDS for the whole sweep; one wave handles one row of a slab, so a row's
+// entries are wave-uniform and the row loop has no divergence.  The running
+// output is read and written with non-temporal accesses so it does not evict
+// the slab.  Rows of internal vectors are padded to a multiple of 64 elements
+// so a slab segment never straddles cache lines shared with the next slab.
+//
+// Epilogues (both passes together):
+//   HV_STORE    y = H x
+//   HV_LANCZOS  y = alpha H x + beta y, partial sums of y.x    (alpha, beta on the device)
+//   HV_RESIDUAL z = H x - alpha x (not stored), partial sums of z.z and x.Hx
+// Partial sums are one FP64 value per slab-pass workgroup, summed later in a
+// fixed order.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hub {
+
+namespace {
+
+constexpr int kSlab = 64;       // slab width in elements = one wave
+constexpr int kSlabThreads = 256;
+constexpr int kLdsBytes = 160 * 1024;
+
+__device__ inline double block_sum2(double v, double *scratch)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        scratch[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; w++)
+            s += scratch[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ inline float flip_sign(float v, uint32_t sg) { return __int_as_float(__float_as_int(v) ^ (int)sg); }
+__device__ inline double flip_sign(double v, uint32_t sg)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ ((long long)sg << 32));
+}
+
+struct RowArgs {
+    const uint4 *__restrict__ groups;  // [g][d] -> 4 entries
+    const uint8_t *__restrict__ nq;    // groups per 64 columns
+    const uint32_t *__restrict__ states_up;
+    const uint32_t *__restrict__ states_dn;
+    int64_t dim_up, dim_dn;
+    int ngroups;
+    double t, U;
+};
+
+// Row pass.  MODE as in the file comment; for HV_RESIDUAL y is the scratch
+// vector z and alpha is the shift.
+template <typename T, int RPB, int MODE>
+__global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__restrict__ x, int64_t ldx,
+                                                       T *__restrict__ y, int64_t ldy, double alpha, double beta,
+                                                       const double *__restrict__ coef)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    if (MODE == HV_LANCZOS) {
+        alpha = coef[0];
+        beta = coef[1];
+    }
+    const int64_t ddn = p.dim_dn;
+    const int64_t slot = ddn + 1;  // staged row length including the zero slot
+    const T mt = (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta;
+
+    for (int64_t r0 = (int64_t)blockIdx.x * RPB; r0 < p.dim_up; r0 += (int64_t)gridDim.x * RPB) {
+        const int nr = (int)min((int64_t)RPB, p.dim_up - r0);
+        for (int64_t i = threadIdx.x; i < ddn * nr; i += blockDim.x) {
+            const int64_t q = i / ddn, d = i - q * ddn;
+            xs[q * slot + d] = x[(r0 + q) * ldx + d];
+        }
+        if (threadIdx.x < RPB)
+            xs[threadIdx.x * slot + ddn] = (T)0;
+        __syncthreads();
+        uint32_t su[RPB];
+#pragma unroll
+        for (int q = 0; q < RPB; q++)
+            su[q] = p.states_up[min(r0 + q, p.dim_up - 1)];
+
+        for (int64_t d0 = 0; d0 < ddn; d0 += blockDim.x) {
+            const int64_t d = d0 + threadIdx.x;
+            const bool ok = d < ddn;
+            const int64_t dd = ok ? d : ddn - 1;
+            const int nq = p.nq[dd >> 6];
+            const uint4 *__restrict__ gp = p.groups + dd;
+            T h[RPB];
+#pragma unroll
+            for (int q = 0; q < RPB; q++)
+                h[q] = (T)0;
+            for (int g0 = 0; g0 < nq; g0 += 8) {
+                uint4 e4[8];
+#pragma unroll
+                for (int g = 0; g < 8; g++)
+                    if (g0 + g < nq)
+                        e4[g] = gp[(int64_t)(g0 + g) * ddn];
+#pragma unroll
+                for (int g = 0; g < 8; g++) {
+                    if (g0 + g < nq) {
+                        const uint32_t ev[4] = {e4[g].x, e4[g].y, e4[g].z, e4[g].w};
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            const uint32_t off = ev[u] & 0x7fffffffu, sg = ev[u] & 0x80000000u;
+#pragma unroll
+                            for (int q = 0; q < RPB; q++) {
+                                const T v = *reinterpret_cast<const T *>(
+                                    reinterpret_cast<const unsigned char *>(xs + q * slot) + off);
+                                h[q] += flip_sign(v, sg);
+                            }
+                        }
+                    }
+                }
+            }
+            if (ok) {
+                const uint32_t sd = p.states_dn[d];
+#pragma unroll
+                for (int q = 0; q < RPB; q++) {
+                    if (q < nr) {
+                        const T xv = xs[q * slot + d];
+                        const T hx = fma(mt, h[q], U * (T)__popc(su[q] & sd) * xv);
+                        T *yp = y + (r0 + q) * ldy + d;
+                        if (MODE == HV_STORE)
+                            *yp = hx;
+                        else if (MODE == HV_LANCZOS)
+                            *yp = a_s * hx + b_s * *yp;
+                        else
+                            *yp = hx - a_s * xv;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+struct SlabArgs {
+    const uint32_t *__restrict__ up_rows;  // row-major entries (column | sign<<31)
+    const uint16_t *__restrict__ nnz_up;
+    int64_t dim_up, dim_dn;
+    int w_up, rows_per_wg, nslab;
+    double t;
+};
+
+// Slab pass.  y holds the row-pass result and receives the complete product.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kSlabThreads) void hv_slabs_kernel(SlabArgs p, const T *__restrict__ x, int64_t ldx,
+                                                                T *__restrict__ y, int64_t ldy, double alpha,
+                                                                const double *__restrict__ coef,
+                                                                double *__restrict__ partials)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint32_t *ent = reinterpret_cast<uint32_t *>(smem_raw);
+    int *nn = reinterpret_cast<int *>(ent + (size_t)p.rows_per_wg * p.w_up);
+    __shared__ double red[4];
+    if (MODE == HV_LANCZOS)
+        alpha = coef[0];
+    const T a_s = (T)alpha, tp = (T)p.t, tm = (T)(-p.t);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int xcd = blockIdx.x & 7;
+    const int64_t local = blockIdx.x >> 3;
+    const int64_t r0 = local * p.rows_per_wg;
+    const int nr = (int)max((int64_t)0, min((int64_t)p.rows_per_wg, p.dim_up - r0));
+    double acc0 = 0.0, acc1 = 0.0;
+
+    for (int i = threadIdx.x; i < nr * p.w_up; i += blockDim.x) {
+        const int q = i / p.w_up, k = i - q * p.w_up;
+        ent[i] = p.up_rows[(r0 + q) * p.w_up + k];
+    }
+    for (int i = threadIdx.x; i < nr; i += blockDim.x)
+        nn[i] = p.nnz_up[r0 + i];
+    __syncthreads();
+
+    constexpr int UNR = 8;
+    for (int s = xcd; s < p.nslab; s += 8) {
+        const int64_t dcol = (int64_t)s * kSlab + lane;
+        const bool okd = dcol < p.dim_dn;
+        const int64_t d = okd ? dcol : p.dim_dn - 1;
+        for (int q = wave; q < nr; q += kSlabThreads / 64) {
+            const int64_t r = r0 + q;
+            const int n = nn[q];
+            const uint32_t *er = ent + (size_t)q * p.w_up;
+            T acc = (T)0;
+            for (int k0 = 0; k0 < n; k0 += UNR) {
+                int64_t c[UNR];
+                T cf[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; u++) {
+                    const bool live = k0 + u < n;
+                    const uint32_t e = er[live ? k0 + u : 0];
+                    c[u] = live ? (int64_t)(e & 0x7fffffffu) : r;
+                    cf[u] = live ? ((e >> 31) ? tp : tm) : (T)0;
+                }
+                T v[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; u++)
+                    v[u] = x[c[u] * ldx + d];
+#pragma unroll
+                for (int u = 0; u < UNR; u++)
+                    acc = fma(cf[u], v[u], acc);
+            }
+            if (okd) {
+                T *yp = y + r * ldy + d;
+                const T prev = __builtin_nontemporal_load(yp);
+                if (MODE == HV_STORE) {
+                    __builtin_nontemporal_store(prev + acc, yp);
+                } else if (MODE == HV_LANCZOS) {
+                    const T q2 = prev + a_s * acc;
+                    __builtin_nontemporal_store(q2, yp);
+                    acc0 += (double)q2 * (double)x[r * ldx + d];
+                } else {
+                    const double z = (double)prev + (double)acc;  // H x - alpha x
+                    const double xv = (double)x[r * ldx + d];
+                    acc0 += z * z;
+                    acc1 += xv * (z + alpha * xv);  // x . H x
+                }
+            }
+        }
+    }
+    if (MODE != HV_STORE) {
+        const double s0 = block_sum2(acc0, red);
+        if (threadIdx.x == 0)
+            partials[blockIdx.x] = s0;
+        if (MODE == HV_RESIDUAL) {
+            const double s1 = block_sum2(acc1, red);
+            if (threadIdx.x == 0)
+                partials[gridDim.x + blockIdx.x] = s1;
+        }
+    }
+}
+
+template <typename T, int RPB>
+size_t row_lds(int64_t ddn)
+{
+    return (size_t)RPB * (size_t)(ddn + 1) * sizeof(T);
+}
+
+}  // namespace
+
+HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
+{
+    HvPlan pl;
+    pl.elem_bytes = elem_bytes;
+    const int64_t ddn = a.dim_dn;
+    const size_t one_row = (size_t)(ddn + 1) * (size_t)elem_bytes;
+    pl.two_pass = one_row <= (size_t)kLdsBytes;
+    if (!pl.two_pass) {
+        pl.ld = ddn;
+        pl.nparts = hv_blocks(a, elem_bytes);
+        return pl;
+    }
+    pl.ld = ((ddn + kSlab - 1) / kSlab) * kSlab;
+    // rows per workgroup in the row pass: as many as fit in LDS, up to 3 (FP32) or 2 (FP64)
+    int rpb = elem_bytes == 4 ? 3 : 2;
+    while (rpb > 1 && one_row * (size_t)rpb > (size_t)kLdsBytes)
+        rpb--;
+    pl.rows_rpb = rpb;
+    pl.rows_lds = one_row * (size_t)rpb;
+    int64_t thr = ((ddn + 63) / 64) * 64;
+    pl.rows_threads = (int)(thr < 1024 ? thr : 1024);
+    int per_cu = 2048 / pl.rows_threads;
+    int by_lds = (int)((size_t)kLdsBytes / pl.rows_lds);
+    per_cu = by_lds < per_cu ? by_lds : per_cu;
+    if (per_cu < 1)
+        per_cu = 1;
+    const int64_t groups = (a.dim_up + rpb - 1) / rpb;
+    const int64_t cap = (int64_t)256 * per_cu;
+    pl.rows_grid = (int)(groups < cap ? groups : cap);
+    // slab pass: 8 XCDs x nw workgroups, each owning a block of rows
+    int64_t nw = a.dim_up < 256 ? a.dim_up : 256;
+    const int64_t wup = a.w_up > 0 ? a.w_up : 1;
+    while (((a.dim_up + nw - 1) / nw) * (wup * 4 + 4) > 48 * 1024)
+        nw *= 2;
+    pl.slab_rw = (int)((a.dim_up + nw - 1) / nw);
+    pl.slab_grid = (int)(8 * nw);
+    pl.slab_lds = (size_t)pl.slab_rw * (size_t)(wup * 4 + 4);
+    pl.nslab = (int)((ddn + kSlab - 1) / kSlab);
+    pl.nparts = pl.slab_grid;
+    return pl;
+}
+
+template <typename T, int RPB>
+static void launch_rows_rpb(const RowArgs &ra, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy,
+                            int mode, double alpha, const double *coef, hipStream_t s)
+{
+    const size_t lds = row_lds<T, RPB>(ra.dim_dn);
+    auto go = [&](auto kern) {
+        HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(pl.rows_grid), dim3(pl.rows_threads), lds, s, ra, x, ldx, y, ldy, alpha, 0.0,
+                           coef);
+        HUB_HIP(hipGetLastError());
+    };
+    if (mode == HV_STORE)
+        go(hv_rows_kernel<T, RPB, HV_STORE>);
+    else if (mode == HV_LANCZOS)
+        go(hv_rows_kernel<T, RPB, HV_LANCZOS>);
+    else
+        go(hv_rows_kernel<T, RPB, HV_RESIDUAL>);
+}
+
+template <typename T>
+void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
+                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s)
+{
+    if (!pl.two_pass) {
+        // rows too wide for LDS: the one-pass kernel (dense rows only)
+        if (mode == HV_RESIDUAL)
+            launch_hv<T>(a, x, nullptr, HV_RESIDUAL, alpha, coef, partials, pl.nparts, s);
+        else
+            launch_hv<T>(a, x, y, mode, alpha, coef, partials, pl.nparts, s);
+        return;
+    }
+    RowArgs ra;
+    ra.groups = sizeof(T) == 8 ? a.dn_groups64 : a.dn_groups32;
+    ra.nq = a.dn_nq;
+    ra.states_up = a.states_up;
+    ra.states_dn = a.states_dn;
+    ra.dim_up = a.dim_up;
+    ra.dim_dn = a.dim_dn;
+    ra.ngroups = a.dn_ngroups;
+    ra.t = a.t;
+    ra.U = a.U;
+    T *yr = mode == HV_RESIDUAL ? scratch : y;
+    const int64_t ldyr = mode == HV_RESIDUAL ? lds_ : ldy;
+    if (pl.rows_rpb == 3)
+        launch_rows_rpb<T, 3>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+    else if (pl.rows_rpb == 2)
+        launch_rows_rpb<T, 2>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+    else
+        launch_rows_rpb<T, 1>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+
+    SlabArgs sa;
+    sa.up_rows = a.up_rows;
+    sa.nnz_up = a.nnz_up;
+    sa.dim_up = a.dim_up;
+    sa.dim_dn = a.dim_dn;
+    sa.w_up = a.w_up > 0 ? a.w_up : 1;
+    sa.rows_per_wg = pl.slab_rw;
+    sa.nslab = pl.nslab;
+    sa.t = a.t;
+    auto go = [&](auto kern) {
+        if (pl.slab_lds > 64 * 1024)
+            HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)pl.slab_lds));
+        hipLaunchKernelGGL(kern, dim3(pl.slab_grid), dim3(kSlabThreads), pl.slab_lds, s, sa, x, ldx, yr, ldyr, alpha,
+                           coef, partials);
+        HUB_HIP(hipGetLastError());
+    };
+    if (mode == HV_STORE)
+        go(hv_slabs_kernel<T, HV_STORE>);
+    else if (mode == HV_LANCZOS)
+        go(hv_slabs_kernel<T, HV_LANCZOS>);
+    else
+        go(hv_slabs_kernel<T, HV_RESIDUAL>);
+}
+
+template void launch_hv2<double>(const HvArgs &, const HvPlan &, const double *, int64_t, double *, int64_t,
+                                 double *, int64_t, int, double, const double *, double *, hipStream_t);
+template void launch_hv2<float>(const HvArgs &, const HvPlan &, const float *, int64_t, float *, int64_t, float *,
+                                int64_t, int, double, const double *, double *, hipStream_t);
+
+}  // namespace hub

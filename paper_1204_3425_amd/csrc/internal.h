@@ -42,6 +42,12 @@ struct DeviceTables {
     uint32_t *up_rows = nullptr;   // row-major: entry k of row r at r*w_up + k (row entries are wave-uniform)
     uint32_t *dn_cols = nullptr;   // column-major: entry k of row d at k*dim_dn + d (coalesced across lanes)
     uint16_t *nnz_up = nullptr, *nnz_dn = nullptr;
+    // down table for the row pass: groups of four entries holding the byte
+    // offset of the source element in a staged row (FP64 and FP32 layouts),
+    // sign in bit 31, padding pointing at the zero slot after the row
+    uint32_t *dn_groups64 = nullptr, *dn_groups32 = nullptr;
+    uint8_t *dn_nq = nullptr;      // groups needed by the 64 columns of a wave
+    int dn_ngroups = 0;
     size_t bytes = 0;
 };
 
@@ -75,9 +81,24 @@ void tridiag_lowest_vector(const double *d, const double *e, int m, double lam, 
 struct HvArgs {
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
+    const uint4 *dn_groups64, *dn_groups32;
+    const uint8_t *dn_nq;
+    int dn_ngroups;
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
     double t, U;
+};
+
+// Launch shape of the two-pass H.v for one element size (hv.hip).
+struct HvPlan {
+    int elem_bytes = 8;
+    bool two_pass = false;  // false: rows too wide for LDS, one-pass kernel
+    int64_t ld = 0;         // row stride of internal vectors (elements)
+    int rows_rpb = 1, rows_threads = 64, rows_grid = 1;
+    size_t rows_lds = 0;
+    int slab_rw = 1, slab_grid = 8, nslab = 1;
+    size_t slab_lds = 0;
+    int nparts = 1;         // partial sums written per reduction
 };
 enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2 };
 enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2 };
@@ -92,14 +113,27 @@ void launch_hv(const HvArgs &a, const T *x, T *y, int mode, double alpha, const 
                int nblocks, hipStream_t s);
 int hv_blocks(const HvArgs &a, int elem_bytes);
 
+HvPlan make_hv_plan(const HvArgs &a, int elem_bytes);
+// x, y (and scratch) are row-major dim_up x dim_dn with row strides ldx, ldy
+// (lds_); scratch (the row-pass output) is used by HV_RESIDUAL only, where y
+// is not written.  Partial sums: pl.nparts values (HV_RESIDUAL: twice that).
+template <typename T>
+void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
+                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s);
+
 template <typename T>
 void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);
 void launch_start_raw(uint64_t seed, double *f, int64_t n, hipStream_t s);
 void launch_start_norm2(const double *given, uint64_t seed, int64_t n, double *partials, int nblocks, hipStream_t s);
+// out[r*ld + d] = (T)(c f[r*dim_dn + d]) and 0 in the row padding; zero (if
+// not NULL) is cleared including its padding
 template <typename T>
-void launch_start_fill(const double *given, uint64_t seed, double c, T *out, T *zero, int64_t n, hipStream_t s);
+void launch_start_fill(const double *given, uint64_t seed, double c, T *out, T *zero, int64_t dim_up, int64_t dim_dn,
+                       int64_t ld, hipStream_t s);
+// psi[r*dim_dn + d] (+)= y_j * coef[0] * v[r*ld + d]
 template <typename T>
-void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int64_t n, bool first, hipStream_t s);
+void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int64_t dim_up, int64_t dim_dn, int64_t ld,
+                    bool first, hipStream_t s);
 void launch_psi_stats(const double *psi, const double *given, uint64_t seed, int64_t n, double *partials, int nblocks,
                       hipStream_t s);
 void launch_scale(double *v, double c, int64_t n, hipStream_t s);

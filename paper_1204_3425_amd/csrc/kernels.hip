@@ -305,52 +305,70 @@ void launch_start_norm2(const double *given, uint64_t seed, int64_t n, double *p
     HUB_HIP(hipGetLastError());
 }
 
-// out = (T)(c f), the normalised start vector f_1 in the working precision;
-// zero = the previous vector f_0 = 0 (Alg. 1), when not NULL.
+// Row-major fills between the dense J order and the padded internal layout.
+#define ROW_LOOP(r, d, dim_up, width)                                                        \
+    for (int64_t r = blockIdx.x; r < (dim_up); r += gridDim.x)                               \
+        for (int64_t d = threadIdx.x; d < (width); d += blockDim.x)
+
+static int row_blocks(int64_t dim_up) { return (int)(dim_up < 4096 ? dim_up : 4096); }
+
+// out = (T)(c f), the normalised start vector f_1 in the working precision and
+// layout (zero in the row padding); zero = the previous vector f_0 = 0 (Alg. 1).
 template <typename T>
 __global__ __launch_bounds__(256) void start_fill_kernel(const double *__restrict__ given, uint64_t seed, double c,
-                                                         T *__restrict__ out, T *__restrict__ zero, int64_t n)
+                                                         T *__restrict__ out, T *__restrict__ zero, int64_t dim_up,
+                                                         int64_t dim_dn, int64_t ld)
 {
-    GRID_STRIDE(i, n)
+    ROW_LOOP(r, d, dim_up, ld)
     {
-        out[i] = (T)(c * start_or_given(given, seed, i));
+        const T v = d < dim_dn ? (T)(c * start_or_given(given, seed, r * dim_dn + d)) : (T)0;
+        out[r * ld + d] = v;
         if (zero)
-            zero[i] = (T)0;
+            zero[r * ld + d] = (T)0;
     }
 }
 
 template <typename T>
-void launch_start_fill(const double *given, uint64_t seed, double c, T *out, T *zero, int64_t n, hipStream_t s)
+void launch_start_fill(const double *given, uint64_t seed, double c, T *out, T *zero, int64_t dim_up, int64_t dim_dn,
+                       int64_t ld, hipStream_t s)
 {
-    hipLaunchKernelGGL(start_fill_kernel<T>, dim3(stream_blocks(n)), dim3(256), 0, s, given, seed, c, out, zero, n);
+    hipLaunchKernelGGL(start_fill_kernel<T>, dim3(row_blocks(dim_up)), dim3(256), 0, s, given, seed, c, out, zero,
+                       dim_up, dim_dn, ld);
     HUB_HIP(hipGetLastError());
 }
-template void launch_start_fill<double>(const double *, uint64_t, double, double *, double *, int64_t, hipStream_t);
-template void launch_start_fill<float>(const double *, uint64_t, double, float *, float *, int64_t, hipStream_t);
+template void launch_start_fill<double>(const double *, uint64_t, double, double *, double *, int64_t, int64_t,
+                                        int64_t, hipStream_t);
+template void launch_start_fill<float>(const double *, uint64_t, double, float *, float *, int64_t, int64_t, int64_t,
+                                       hipStream_t);
 
 // psi += y_j * (1/s) * v, where v holds s f_j and 1/s is the device scalar
 // coef[0] (the ground-state vector sum_j y_j f_j of the replayed recurrence).
 template <typename T>
 __global__ __launch_bounds__(256) void psi_acc_kernel(double *__restrict__ psi, const T *__restrict__ v, double yj,
-                                                      const double *__restrict__ coef, int64_t n, int first)
+                                                      const double *__restrict__ coef, int64_t dim_up, int64_t dim_dn,
+                                                      int64_t ld, int first)
 {
     const double c = yj * coef[0];
-    GRID_STRIDE(i, n)
+    ROW_LOOP(r, d, dim_up, dim_dn)
     {
-        const double add = c * (double)v[i];
-        psi[i] = first ? add : psi[i] + add;
+        const double add = c * (double)v[r * ld + d];
+        double *p = psi + r * dim_dn + d;
+        *p = first ? add : *p + add;
     }
 }
 
 template <typename T>
-void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int64_t n, bool first, hipStream_t s)
+void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int64_t dim_up, int64_t dim_dn, int64_t ld,
+                    bool first, hipStream_t s)
 {
-    hipLaunchKernelGGL(psi_acc_kernel<T>, dim3(stream_blocks(n)), dim3(256), 0, s, psi, v, yj, coef, n,
-                       first ? 1 : 0);
+    hipLaunchKernelGGL(psi_acc_kernel<T>, dim3(row_blocks(dim_up)), dim3(256), 0, s, psi, v, yj, coef, dim_up, dim_dn,
+                       ld, first ? 1 : 0);
     HUB_HIP(hipGetLastError());
 }
-template void launch_psi_acc<double>(double *, const double *, double, const double *, int64_t, bool, hipStream_t);
-template void launch_psi_acc<float>(double *, const float *, double, const double *, int64_t, bool, hipStream_t);
+template void launch_psi_acc<double>(double *, const double *, double, const double *, int64_t, int64_t, int64_t, bool,
+                                     hipStream_t);
+template void launch_psi_acc<float>(double *, const float *, double, const double *, int64_t, int64_t, int64_t, bool,
+                                    hipStream_t);
 
 // partial sums of psi.psi and psi.f1
 __global__ __launch_bounds__(256) void psi_stats_kernel(const double *__restrict__ psi, const double *__restrict__ given,

@@ -236,8 +236,15 @@ def test_lanczos_4x4_against_golden():
     _say("lanczos 4x4 fp64", n)
     got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, -1.0, n)
     assert got["n_iter"] == g["n_iter"]
-    assert np.allclose(got["a"][:20], g["a"][:20], rtol=1e-12, atol=1e-13)
-    assert np.allclose(got["b"][:20], g["b"][:20], rtol=1e-12, atol=1e-13)
+    # Each a_j, b_{j+1} is a dot product over dim = 1.66e8 terms; two summation
+    # orders differ by about sqrt(dim) * eps ~ 1.4e-12 relative per step, and the
+    # recurrence carries that forward, so the first 20 steps are compared at
+    # 64 sqrt(dim) eps (= 9e-11) rather than the small-sector 1e-12.
+    rtol = 64 * math.sqrt(p.dim) * np.finfo(np.float64).eps
+    da = np.abs(got["a"][:20] - g["a"][:20]) / np.abs(np.asarray(g["a"][:20]))
+    db = np.abs(got["b"][:20] - g["b"][:20]) / np.abs(np.asarray(g["b"][:20]))
+    _say("4x4 first-20 max rel diff a %.2e b %.2e (tol %.2e)" % (da.max(), db.max(), rtol))
+    assert da.max() <= rtol and db.max() <= rtol
     assert got["E0"] == pytest.approx(g["E0"], rel=1e-10)
     _say("lanczos 4x4 mixed", n)
     mix = _lanczos_gpu(h, p, hb.HUBBARD_MIXED, -1.0, n)
