@@ -1,20 +1,33 @@
 """Benchmark of the Hubbard exact-diagonalisation hot path on one MI355X.
 
 Workload: the 4x4 periodic square lattice at half filling (8 up + 8 down
-electrons, t = 1, U = 8; dim = 12870^2 = 165,636,900), seeded synthetic start
-vector.  One step = one Lanczos iteration of Alg. 1 (fused H.v with the
-three-term update, the a_j / b_{j+1} reductions, the q - a_j f_j update and
-the host tridiagonal solve).
+electrons, t = 1, U = 8; dim = 12870^2 = 165,636,900), seeded SplitMix64
+start vector.  One step = one Lanczos iteration of Alg. 1 (the H.v of the
+step with the three-term update fused into it, the a_j / b_{j+1}
+reductions, the q - a_j f_j update and the host tridiagonal solve).
 
 Printed JSON line (one):
   value          H.v algorithmic bandwidth in GB/s, FP64: 2 * dim * 8 bytes
-                 (x read once, y written once) / mean H.v kernel time
+                 (x read once, y written once) / mean H.v time, where one H.v
+                 is the row-pass and slab-pass launches together
   ms_per_step    FP64 Lanczos iteration time
   lanczos_*      Lanczos iterations/s in FP64 and in mixed precision
-  roofline       the H.v kernel against the 8 TB/s HBM peak
-  cpu_baseline   the sequential FP64 oracle on one host core, on a bounded sample
+  roofline       H.v against the 8 TB/s HBM peak; traffic from the stored
+                 rocprofv3 FETCH_SIZE / WRITE_SIZE counts when they were taken
+                 on the current kernel sources, else null
+  cpu_baseline   the sequential FP64 oracle on one host core, bounded sample
+
+Other modes:
+  --calibrate-copy           also run one device copy of known size (for counter scaling)
+  --summarize-trace DIR      print a summary of a rocprofv3 --kernel-trace --stats run
+  --summarize-pmc FETCH_DIR WRITE_DIR
+                             print per-H.v FETCH_SIZE / WRITE_SIZE scaled by the copy
+                             calibration, in the key-value form read back into `traffic`
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -25,32 +38,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H·v HBM GB/s + Lanczos iters/s, 4x4 Hubbard; batched p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hv_square4x4_traffic.txt")
+HV_SOURCES = [os.path.join(ROOT, "paper_1204_3425_amd", "csrc", f) for f in ("hv.hip", "kernels.hip")]
+COPY_BYTES = 1 << 30  # one copy of 1 GiB for counter calibration
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_apply(hb, torch, h, precision, steps, warmup):
-    """Mean duration of one H.v kernel, from HIP events on the launch stream."""
+def source_hash():
+    h = hashlib.sha256()
+    for f in HV_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_hv(hb, torch, h, precision, launches, warmup):
+    """Mean time of one H.v (row pass + slab pass) on padded rows, from HIP
+    events recorded on the stream the kernels run on."""
     hb.hubbard_set_precision(h, precision)
+    ld = hb.hubbard_info(h)["ld_pref"]
     dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
-    x = torch.empty(h.dim, dtype=dt, device="cuda:0")
-    y = torch.empty_like(x)
     f = torch.empty(h.dim, dtype=torch.float64, device="cuda:0")
     hb.hubbard_start_raw(12043425, h.dim, f)
-    x.copy_(f)
+    x = torch.zeros((h.dim_up, ld), dtype=dt, device="cuda:0")
+    x[:, :h.dim_dn] = f.view(h.dim_up, h.dim_dn)
     del f
+    y = torch.zeros_like(x)
     for _ in range(warmup):
-        hb.hubbard_apply(h, x, y)
+        hb.hubbard_apply_ld(h, x, ld, y, ld)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
-        hb.hubbard_apply(h, x, y)
+    for _ in range(launches):
+        hb.hubbard_apply_ld(h, x, ld, y, ld)
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps * 1e-3
+    return e0.elapsed_time(e1) / launches * 1e-3
 
 
 def time_lanczos(hb, torch, h, precision, steps, warmup, seed):
@@ -60,24 +86,123 @@ def time_lanczos(hb, torch, h, precision, steps, warmup, seed):
     t0 = time.perf_counter()
     r = hb.hubbard_lanczos_ex(h, tol=-1.0, max_iter=steps, precision=precision, seed=seed)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt, r
+    return time.perf_counter() - t0, r
 
 
 def cpu_baseline(p):
     """The oracle, as it stands, on one host core: one Lanczos iteration of the
-    same sector (model build and start vector excluded)."""
-    import numpy as np  # noqa: F401
+    same sector (model build and start vector outside the timing)."""
     import oracle
     m = oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
     f1 = oracle.start_vector(p.seed, m.dim)
     t0 = time.perf_counter()
     m.lanczos(f1, tol=-1.0, max_iter=1)
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "Lanczos iters/s", "cores": 1, "kind": "oracle",
-            "sample": "1 FP64 Lanczos iteration (H.v + 3 vector passes) of the 4x4 8u8d sector, "
-                      "single thread, gcc -O2; %.1f s" % dt}
+    return {"value": round(1.0 / dt, 4), "unit": "Lanczos iters/s", "cores": 1, "kind": "oracle",
+            "sample": "1 FP64 Lanczos iteration (one H.v and the vector passes) of the 4x4 8u8d sector, "
+                      "single thread, gcc -O2: %.1f s" % dt}
 
+
+def stored_traffic(dim):
+    """HBM bytes per H.v from the stored counter summary, if it matches the sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for ln in fh:
+            parts = ln.split()
+            if len(parts) >= 2 and not ln.startswith("#"):
+                kv[parts[0]] = parts[1]
+    if kv.get("source_sha") != source_hash() or int(kv.get("dim", 0)) != dim:
+        return None
+    return float(kv["fp64_hbm_bytes_per_hv"])
+
+
+# ------------------------------------------------------------------ summaries
+
+def _kernel_family(name):
+    for fam in ("hv_rows_kernel", "hv_slabs_kernel", "hv_kernel", "axpy_norm_kernel", "reduce_kernel",
+                "start_fill_kernel", "psi_acc_kernel", "copyBuffer", "elementwise"):
+        if fam in name:
+            prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
+            mode = ""
+            if fam in ("hv_rows_kernel", "hv_slabs_kernel"):
+                inner = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "")
+                mode = {"0": "store", "1": "lanczos", "2": "residual"}.get(inner.split(",")[-1], "")
+            return " ".join(x for x in (fam, prec, mode) if x)
+    return name[:60]
+
+
+def summarize_trace(d):
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no kernel_stats.csv under " + d)
+    rows = list(csv.DictReader(open(files[0])))
+    agg = {}
+    for r in rows:
+        fam = _kernel_family(r["Name"])
+        a = agg.setdefault(fam, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+    total = sum(v[1] for v in agg.values())
+    print("%-40s %8s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_ms", "share"))
+    for fam, (calls, tot) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print("%-40s %8d %12.1f %12.2f %6.1f%%" % (fam, calls, tot / calls / 1e3, tot / 1e6, 100 * tot / total))
+
+
+def _pmc_per_kernel(d, counter):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under " + d)
+    acc = {}
+    for r in csv.DictReader(open(files[0])):
+        if r["Counter_Name"] != counter:
+            continue
+        fam = _kernel_family(r["Kernel_Name"])
+        a = acc.setdefault(fam, [0, 0.0])
+        a[0] += 1
+        a[1] += float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+    return {k: (n, tot / n) for k, (n, tot) in acc.items()}
+
+
+def _largest_dispatch(d, counter, name_part):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    best = None
+    for r in csv.DictReader(open(files[0])):
+        if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+            v = float(r["Counter_Value"]) * 1024.0
+            best = v if best is None or v > best else best
+    return best
+
+
+def summarize_pmc(dfetch, dwrite):
+    fetch = _pmc_per_kernel(dfetch, "FETCH_SIZE")
+    write = _pmc_per_kernel(dwrite, "WRITE_SIZE")
+    # the calibration copy is the largest single copyBuffer dispatch of the run
+    cf = _largest_dispatch(dfetch, "FETCH_SIZE", "copyBuffer")
+    cw = _largest_dispatch(dwrite, "WRITE_SIZE", "copyBuffer")
+    sf = COPY_BYTES / cf if cf else 1.0
+    sw = COPY_BYTES / cw if cw else 1.0
+    print("# rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch, scaled by a %d-byte device copy" % COPY_BYTES)
+    print("# copy kernel read  %.4g B -> scale %.4f" % (cf or 0, sf))
+    print("# copy kernel write %.4g B -> scale %.4f" % (cw or 0, sw))
+    print("# %-34s %6s %14s %14s" % ("kernel", "calls", "fetch_GB", "write_GB"))
+    for k in sorted(set(fetch) | set(write)):
+        nf, bf = fetch.get(k, (0, 0.0))
+        nw, bw = write.get(k, (0, 0.0))
+        print("# %-34s %6d %14.4f %14.4f" % (k, max(nf, nw), bf * sf / 1e9, bw * sw / 1e9))
+    hv = 0.0
+    for k in ("hv_rows_kernel f64 store", "hv_slabs_kernel f64 store"):
+        hv += fetch.get(k, (0, 0.0))[1] * sf + write.get(k, (0, 0.0))[1] * sw
+    import workload
+    print("source_sha", source_hash())
+    print("dim", workload.square4x4().dim)
+    print("fp64_hbm_bytes_per_hv", "%.6g" % hv)
+    print("copy_scale_fetch", "%.6g" % sf)
+    print("copy_scale_write", "%.6g" % sw)
+
+
+# ------------------------------------------------------------------ main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -85,7 +210,16 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--summarize-trace")
+    ap.add_argument("--summarize-pmc", nargs=2)
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -99,12 +233,18 @@ def main():
     log("building", p.name)
     h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
     hb.hubbard_set_stream(h, torch.cuda.current_stream().cuda_stream)
-    info = hb.hubbard_info(h)
+
+    if args.calibrate_copy:
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     res = {}
     for name, prec, es in (("fp64", hb.HUBBARD_FP64, 8), ("mixed", hb.HUBBARD_MIXED, 4)):
         log("timing H.v", name)
-        t_hv = time_apply(hb, torch, h, prec, max(10, args.steps // 4), 3)
+        t_hv = time_hv(hb, torch, h, prec, max(10, args.steps // 4), 3)
         log("timing Lanczos", name, args.steps, "steps")
         t_lz, r = time_lanczos(hb, torch, h, prec, args.steps, args.warmup, p.seed)
         res[name] = {"hv_s": t_hv, "hv_gbs": 2.0 * p.dim * es / t_hv / 1e9, "lanczos_s": t_lz,
@@ -113,7 +253,7 @@ def main():
             "Lanczos %.3f ms/iter, E0 %.12f" % (t_lz / r["n_iter"] * 1e3, r["E0"]))
 
     f64 = res["fp64"]
-    ms_step = f64["lanczos_s"] / f64["iters"] * 1e3
+    traffic = stored_traffic(p.dim)
     out = {
         "metric": METRIC,
         "value": round(f64["hv_gbs"], 1),
@@ -121,29 +261,32 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(f64["lanczos_s"] / f64["iters"] * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "4x4 periodic square lattice, 8 up + 8 down, t=1, U=8, dim 165,636,900; "
-                               "seeded SplitMix64 start vector; %d Lanczos iterations" % args.steps,
-                   "dim": p.dim, "precision": "fp64 (mixed reported beside)"},
+                               "seeded SplitMix64 start vector; %d Lanczos iterations per precision" % args.steps,
+                   "dim": p.dim, "precision": "fp64 value; mixed (fp32 H.v, fp64 reductions) beside"},
         "lanczos_iters_per_s": {k: round(v["iters"] / v["lanczos_s"], 2) for k, v in res.items()},
+        "lanczos_ms_per_iter": {k: round(v["lanczos_s"] / v["iters"] * 1e3, 4) for k, v in res.items()},
         "hv_us": {k: round(v["hv_s"] * 1e6, 1) for k, v in res.items()},
         "hv_gbs": {k: round(v["hv_gbs"], 1) for k, v in res.items()},
         "E0": {k: v["E0"] for k, v in res.items()},
         "roofline": {"bound": "hbm", "achieved": round(f64["hv_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(f64["hv_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "hv_kernel (FP64 H.v, store mode)",
+                     "frac": round(f64["hv_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes per H.v (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_over_algorithmic": None if traffic is None else round(traffic / (2 * p.dim * 8), 3),
+                     "kernel": "FP64 H.v = hv_rows_kernel + hv_slabs_kernel (store mode, padded rows)",
                      "algorithmic_bytes_per_launch": 2 * p.dim * 8},
-        "table_bytes": info["device_bytes"],
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one core)")
         cb = cpu_baseline(p)
-        cb["gpu_fp64_vs_cpu"] = round(out["lanczos_iters_per_s"]["fp64"] / cb["value"], 1)
+        cb["gpu_fp64_over_cpu"] = round(out["lanczos_iters_per_s"]["fp64"] / cb["value"], 1)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 

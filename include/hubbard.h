@@ -73,6 +73,7 @@ typedef struct {
     int64_t nnz_up, nnz_dn;      /* stored hopping entries per spin */
     size_t device_bytes;         /* device memory held by the handle (tables + states) */
     size_t vector_bytes;         /* device memory one Lanczos run allocates (work vectors) */
+    int64_t ld_pref;             /* row stride (elements) of the library's own vectors */
 } hubbard_info_t;
 
 typedef struct {
@@ -133,6 +134,14 @@ int hubbard_set_seed(hubbard_h h, uint64_t seed);
  * HUBBARD_FP64 and float under HUBBARD_MIXED; y is overwritten and must not
  * overlap x.  Asynchronous on the handle's stream. */
 int hubbard_apply(hubbard_h h, const void *x, void *y);
+
+/* y = H x as hubbard_apply, with x and y stored as dim_up rows of dim_dn
+ * elements at row strides ldx and ldy (elements, >= dim_dn; the subvectors of
+ * Sec. 4.3, Fig. slots).  Padding elements are neither read nor written.
+ * hubbard_info gives the stride the library uses for its own vectors
+ * (ld_pref): rows that start on 256-byte boundaries let the up-spin pass keep
+ * whole cache lines per slab. */
+int hubbard_apply_ld(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t ldy);
 
 /* Lanczos ground state (Sec. 2.2, Alg. 1, two-vector form): iterates until
  * the energy test passes with tol (> 0), b_{j+1} vanishes, or max_iter (>= 1)

@@ -50,7 +50,8 @@ class hubbard_info_t(ctypes.Structure):
                 ("n_edges", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_double),
                 ("dim_up", ctypes.c_int64), ("dim_dn", ctypes.c_int64), ("dim", ctypes.c_int64),
                 ("w_up", ctypes.c_int32), ("w_dn", ctypes.c_int32), ("nnz_up", ctypes.c_int64),
-                ("nnz_dn", ctypes.c_int64), ("device_bytes", ctypes.c_size_t), ("vector_bytes", ctypes.c_size_t)]
+                ("nnz_dn", ctypes.c_int64), ("device_bytes", ctypes.c_size_t), ("vector_bytes", ctypes.c_size_t),
+                ("ld_pref", ctypes.c_int64)]
 
 
 class hubbard_opts(ctypes.Structure):
@@ -86,6 +87,7 @@ def _load():
         "hubbard_set_precision": [vp, i32],
         "hubbard_set_seed": [vp, u64],
         "hubbard_apply": [vp, vp, vp],
+        "hubbard_apply_ld": [vp, vp, i64, vp, i64],
         "hubbard_lanczos": [vp, dbl, i32, ctypes.POINTER(dbl), vp],
         "hubbard_lanczos_ex": [vp, ctypes.POINTER(hubbard_opts), ctypes.POINTER(hubbard_result)],
         "hubbard_info": [vp, ctypes.POINTER(hubbard_info_t)],
@@ -163,7 +165,7 @@ class Handle:
 
     def __del__(self):
         p = getattr(self, "ptr", None)
-        if p:
+        if p and _lib is not None:
             _lib.hubbard_free(p)
             self.ptr = None
 
@@ -214,6 +216,20 @@ def hubbard_apply(h: Handle, x, y, stream="current"):
     xp = _dev_ptr(x, h.vec_dtype, h.dim, "x")
     yp = _dev_ptr(y, h.vec_dtype, h.dim, "y")
     _check(_lib.hubbard_apply(h, xp, yp), "hubbard_apply")
+
+
+def hubbard_apply_ld(h: Handle, x, ldx: int, y, ldy: int, stream="current"):
+    """y = H x with x, y stored as dim_up rows at strides ldx, ldy (elements)."""
+    if stream == "current":
+        hubbard_set_stream(h, _current_stream())
+    nx = (h.dim_up - 1) * ldx + h.dim_dn
+    ny = (h.dim_up - 1) * ldy + h.dim_dn
+    xp = _dev_ptr(x, h.vec_dtype, None, "x")
+    yp = _dev_ptr(y, h.vec_dtype, None, "y")
+    for t, need, what in ((x, nx, "x"), (y, ny, "y")):
+        if not isinstance(t, int) and t.numel() < need:
+            raise ValueError("%s needs at least %d elements for this stride" % (what, need))
+    _check(_lib.hubbard_apply_ld(h, xp, int(ldx), yp, int(ldy)), "hubbard_apply_ld")
 
 
 def hubbard_lanczos(h: Handle, tol: float, max_iter: int, psi=None, stream="current"):

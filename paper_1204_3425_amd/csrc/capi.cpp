@@ -521,29 +521,50 @@ int hubbard_set_seed(hubbard_h h, uint64_t seed)
     });
 }
 
+static int apply_impl(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t ldy)
+{
+    check_handle(h);
+    if (!x || !y)
+        fail(HUBBARD_EINVAL, "x and y must be device pointers");
+    const int64_t ddn = h->dn.dim;
+    if (ldx < ddn || ldy < ddn)
+        fail(HUBBARD_EINVAL, "row strides must be >= dim_dn");
+    const size_t es = h->precision == HUBBARD_FP64 ? 8 : 4;
+    const char *xb = static_cast<const char *>(x);
+    const char *yb = static_cast<const char *>(y);
+    const size_t xbytes = es * (size_t)((h->up.dim - 1) * ldx + ddn);
+    const size_t ybytes = es * (size_t)((h->up.dim - 1) * ldy + ddn);
+    if (xb < yb + ybytes && yb < xb + xbytes)
+        fail(HUBBARD_EINVAL, "x and y overlap");
+    use_device(h);
+    const HvArgs a = hv_args(h);
+    if (h->precision == HUBBARD_FP64) {
+        const HvPlan pl = make_hv_plan(a, 8);
+        if (!pl.two_pass && (ldx != ddn || ldy != ddn))
+            fail(HUBBARD_EINVAL, "rows too wide for the staged kernels: only dense rows (ld = dim_dn) are supported");
+        launch_hv2<double>(a, pl, static_cast<const double *>(x), ldx, static_cast<double *>(y), ldy, nullptr, 0,
+                           HV_STORE, 0.0, nullptr, nullptr, h->stream);
+    } else {
+        const HvPlan pl = make_hv_plan(a, 4);
+        if (!pl.two_pass && (ldx != ddn || ldy != ddn))
+            fail(HUBBARD_EINVAL, "rows too wide for the staged kernels: only dense rows (ld = dim_dn) are supported");
+        launch_hv2<float>(a, pl, static_cast<const float *>(x), ldx, static_cast<float *>(y), ldy, nullptr, 0,
+                          HV_STORE, 0.0, nullptr, nullptr, h->stream);
+    }
+    return HUBBARD_OK;
+}
+
 int hubbard_apply(hubbard_h h, const void *x, void *y)
 {
     return guarded([&]() -> int {
         check_handle(h);
-        if (!x || !y)
-            fail(HUBBARD_EINVAL, "x and y must be device pointers");
-        const size_t es = h->precision == HUBBARD_FP64 ? 8 : 4;
-        const char *xb = static_cast<const char *>(x);
-        const char *yb = static_cast<const char *>(y);
-        const size_t bytes = es * (size_t)h->dim;
-        if (xb < yb + bytes && yb < xb + bytes)
-            fail(HUBBARD_EINVAL, "x and y overlap");
-        use_device(h);
-        const HvArgs a = hv_args(h);
-        const int64_t ddn = h->dn.dim;
-        if (h->precision == HUBBARD_FP64)
-            launch_hv2<double>(a, make_hv_plan(a, 8), static_cast<const double *>(x), ddn, static_cast<double *>(y), ddn,
-                               nullptr, 0, HV_STORE, 0.0, nullptr, nullptr, h->stream);
-        else
-            launch_hv2<float>(a, make_hv_plan(a, 4), static_cast<const float *>(x), ddn, static_cast<float *>(y), ddn,
-                              nullptr, 0, HV_STORE, 0.0, nullptr, nullptr, h->stream);
-        return HUBBARD_OK;
+        return apply_impl(h, x, h->dn.dim, y, h->dn.dim);
     });
+}
+
+int hubbard_apply_ld(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t ldy)
+{
+    return guarded([&]() -> int { return apply_impl(h, x, ldx, y, ldy); });
 }
 
 int hubbard_lanczos(hubbard_h h, double tol, int max_iter, double *E0, double *psi)
@@ -600,7 +621,9 @@ int hubbard_info(hubbard_h h, hubbard_info_t *info)
         r.nnz_up = h->up.nnz;
         r.nnz_dn = h->dn.nnz;
         r.device_bytes = h->dev.bytes;
-        r.vector_bytes = (size_t)h->dim * (h->precision == HUBBARD_FP64 ? 16 : 8);
+        const HvPlan pl = make_hv_plan(hv_args(h), h->precision == HUBBARD_FP64 ? 8 : 4);
+        r.ld_pref = pl.ld;
+        r.vector_bytes = (size_t)h->up.dim * (size_t)pl.ld * (h->precision == HUBBARD_FP64 ? 16 : 8);
         *info = r;
         return HUBBARD_OK;
     });

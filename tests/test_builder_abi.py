@@ -155,3 +155,18 @@ def test_precision_and_seed_setters():
     hb.hubbard_set_seed(h, 5)
     with pytest.raises(hb.HubbardError):
         hb.hubbard_set_precision(h, 7)
+
+
+def test_apply_ld_validates_strides_before_touching_the_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("uses made-up device addresses; run only where no GPU is present")
+    h = hb.hubbard_build(6, workload.ring(6), 3, 3, 1.0, 2.0)
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    lib.hubbard_apply_ld.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]
+    # stride shorter than a row
+    assert lib.hubbard_apply_ld(h.ptr, 4096, h.dim_dn - 1, 1 << 30, h.dim_dn) == hb.HUBBARD_EINVAL
+    # overlapping rows of x and y
+    assert lib.hubbard_apply_ld(h.ptr, 4096, h.dim_dn, 4096 + 8, h.dim_dn) == hb.HUBBARD_EINVAL
+    info = hb.hubbard_info(h)
+    assert info["ld_pref"] >= h.dim_dn and info["ld_pref"] % 64 == 0

@@ -130,6 +130,29 @@ def test_apply_4x4_sampled_rows(precision):
     assert abs(lhs - rhs) <= tol * (np.abs(u).sum() + np.abs(x).sum())
 
 
+@pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("pad", [0, 3, 64])
+def test_apply_strided_rows_equal_dense(precision, pad):
+    """hubbard_apply_ld on padded rows gives bitwise the dense result, and
+    leaves the padding untouched."""
+    p = workload.problem("torus3x4", 12, workload.torus(3, 4), 5, 6, 1.0, 8.0)
+    h = _build(p)
+    hb.hubbard_set_precision(h, precision)
+    dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
+    info = hb.hubbard_info(h)
+    ld = info["ld_pref"] + pad
+    x = torch.from_numpy(workload.random_vector(p.dim, 5)).to(DEV, dt)
+    y = torch.empty_like(x)
+    hb.hubbard_apply(h, x, y)
+    xp = torch.full((p.dim_up, ld), 7.0, dtype=dt, device=DEV)
+    xp[:, :p.dim_dn] = x.view(p.dim_up, p.dim_dn)
+    yp = torch.full((p.dim_up, ld), -3.0, dtype=dt, device=DEV)
+    hb.hubbard_apply_ld(h, xp, ld, yp, ld)
+    torch.cuda.synchronize()
+    assert torch.equal(yp[:, :p.dim_dn].reshape(-1), y)
+    assert bool((yp[:, p.dim_dn:] == -3.0).all())
+
+
 def test_apply_rejects_overlap_and_bad_tensors():
     p = workload.ring8()
     h = _build(p)
