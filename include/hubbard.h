@@ -92,7 +92,8 @@ typedef struct {
     double e0;          /* lowest eigenvalue of T_m (Sec. 2.2, eq. Tmatrix) */
     double residual;    /* FP64 ||H psi - e0 psi|| when psi was requested, else -1 */
     double rayleigh;    /* FP64 <psi|H|psi> when psi was requested, else NaN */
-    double err_est;     /* residual / max(1, |e0|) when psi was requested, else -1 */
+    double err_est;     /* residual / max(1, |e0|) when psi was requested; otherwise the Lanczos
+                           estimate b_{m+1} |y_m| / max(1, |e0|) of that residual (y: eigenvector of T_m) */
     double seconds;     /* wall time of the whole call */
     double seconds_per_iter; /* mean wall time of one Lanczos step (first pass) */
     int32_t n_iter;     /* m = number of a_j computed */
@@ -171,12 +172,75 @@ int hubbard_export_table(hubbard_h h, int spin, int32_t *col, int8_t *sgn);
  * f: device FP64 array.  Asynchronous on `hip_stream`. */
 int hubbard_start_raw(uint64_t seed, int64_t dim, double *f, void *hip_stream);
 
-/* Runs n independent Lanczos solves (one per handle, each with opts[i]) as one
- * batch on the current device, writing res[i].  Small sectors share launches so
- * the GPU stays busy (Sec. 5 notes that small systems leave it idle).  Every
- * result equals, within the stated tolerance, the same solve run alone.
- * Synchronous.  Returns the most severe per-solve status. */
+/* Runs n independent Lanczos solves (one per handle, each with opts[i]) on the
+ * current device, writing res[i].  Solves without a psi request whose rows fit
+ * in 64 KB share their launches: every step of every such solve runs in the
+ * same four kernel launches (Sec. 5 notes that small systems leave the GPU
+ * idle).  The others run one after another.  A batched result does not depend
+ * on which other solves share the batch, and agrees with the same solve run
+ * alone within rounding.  Synchronous; the stream of hs[0] is used.  Returns the
+ * most severe per-solve status. */
 int hubbard_lanczos_batch(hubbard_h *hs, int n, const hubbard_opts *opts, hubbard_result *res);
+
+/* ---------------------------------------------------------------- serving
+ * A server runs a continuous stream of independent ground-state requests on
+ * the current device.  Requests are admitted first-fit in arrival order while
+ * a slot is free and their device footprint (tables + work vectors, an upper
+ * bound from the sector size) fits in the HBM budget; admitted requests have
+ * their tables built on a host thread and then join the running work: small
+ * sectors join a shared batch between Lanczos steps (every step of every
+ * batched request runs in the same kernel launches), large ones run on a
+ * second stream with the two-pass H.v, so both overlap on the device.  A
+ * result does not depend on what else was running.  The caller polls
+ * completions, which carry the result and the submit/admit/start/done times. */
+typedef struct hubbard_server *hubbard_server_h;
+
+typedef struct {
+    int32_t sites;          /* as hubbard_build */
+    const int32_t *edges;   /* 2*n_edges site indices; copied by submit */
+    int32_t n_edges;
+    int32_t n_up, n_dn;
+    double t, U;
+    double tol;             /* as hubbard_opts */
+    int32_t max_iter;
+    int32_t precision;
+    uint64_t seed;
+    uint64_t tag;           /* caller's value, returned in the completion */
+} hubbard_request;
+
+typedef struct {
+    uint64_t id, tag;
+    int32_t status;         /* OK / ENOCONV, or the error that ended the request (ENOMEM when it can never fit) */
+    int32_t pad_;
+    double t_submit, t_admit, t_start, t_done;  /* seconds since the server was created */
+    hubbard_result result;  /* psi is never requested; err_est is the Lanczos residual estimate */
+} hubbard_completion;
+
+typedef struct {
+    uint64_t budget, reserved, peak_reserved;   /* bytes */
+    uint64_t submitted, admitted, completed, rejected, pending;
+    int32_t max_active_batch, slots_used;
+} hubbard_server_stats_t;
+
+/* Creates a server with an HBM budget (bytes, > 0) and a slot limit (>= 1). */
+int hubbard_server_create(size_t hbm_budget, int max_slots, hubbard_server_h *out);
+/* Queues one request and returns its id.  EINVAL for malformed requests; a
+ * request whose footprint exceeds the whole budget completes at once with
+ * status ENOMEM.  Thread-safe. */
+int hubbard_server_submit(hubbard_server_h s, const hubbard_request *req, uint64_t *id);
+/* Copies up to cap completions into out (host) and sets *n; waits up to
+ * timeout_us when none is ready.  Thread-safe. */
+int hubbard_server_poll(hubbard_server_h s, hubbard_completion *out, int cap, int *n, int timeout_us);
+int hubbard_server_stats(hubbard_server_h s, hubbard_server_stats_t *stats);
+/* Stops the server: running requests are abandoned, queued ones dropped. */
+int hubbard_server_destroy(hubbard_server_h s);
+
+/* The admission rule of the server, exposed for schedulers and tests: given
+ * the footprints of n queued requests in arrival order, marks admit[k] = 1 for
+ * each request taken first-fit while fewer than free_slots are taken and the
+ * taken footprints fit in budget - used.  Returns the number taken. */
+int hubbard_admission_plan(const uint64_t *footprints, int n, uint64_t budget, uint64_t used, int free_slots,
+                           int32_t *admit);
 
 /* Message for a return code, and the message of the calling thread's last
  * failure (empty when none). */

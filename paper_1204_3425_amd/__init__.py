@@ -67,6 +67,26 @@ class hubbard_result(ctypes.Structure):
                 ("precision", ctypes.c_int32)]
 
 
+class hubbard_request(ctypes.Structure):
+    _fields_ = [("sites", ctypes.c_int32), ("edges", ctypes.c_void_p), ("n_edges", ctypes.c_int32),
+                ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("tag", ctypes.c_uint64)]
+
+
+class hubbard_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("result", hubbard_result)]
+
+
+class hubbard_server_stats_t(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_uint64), ("reserved", ctypes.c_uint64), ("peak_reserved", ctypes.c_uint64),
+                ("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("pending", ctypes.c_uint64), ("max_active_batch", ctypes.c_int32),
+                ("slots_used", ctypes.c_int32)]
+
+
 def _load():
     # One HIP runtime per process: torch ships its own libamdhip64.so.7, and
     # loading it first makes this library bind to that same instance (the
@@ -95,6 +115,12 @@ def _load():
         "hubbard_export_table": [vp, i32, vp, vp],
         "hubbard_start_raw": [u64, i64, vp, vp],
         "hubbard_lanczos_batch": [vp, i32, ctypes.POINTER(hubbard_opts), ctypes.POINTER(hubbard_result)],
+        "hubbard_server_create": [ctypes.c_size_t, i32, ctypes.POINTER(vp)],
+        "hubbard_server_submit": [vp, ctypes.POINTER(hubbard_request), ctypes.POINTER(ctypes.c_uint64)],
+        "hubbard_server_poll": [vp, ctypes.POINTER(hubbard_completion), i32, ctypes.POINTER(ctypes.c_int), i32],
+        "hubbard_server_stats": [vp, ctypes.POINTER(hubbard_server_stats_t)],
+        "hubbard_server_destroy": [vp],
+        "hubbard_admission_plan": [vp, i32, ctypes.c_uint64, ctypes.c_uint64, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -332,9 +358,82 @@ def hubbard_start_raw(seed: int, dim: int, f, stream="current"):
            "hubbard_start_raw")
 
 
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Owns one continuous-batching server (hubbard_server_destroy on close)."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.hubbard_server_destroy(self.ptr)
+            self.ptr = None
+
+    @property
+    def _as_parameter_(self):
+        if not self.ptr:
+            raise ValueError("server already destroyed")
+        return ctypes.c_void_p(self.ptr)
+
+
+def hubbard_server_create(hbm_budget: int, max_slots: int) -> Server:
+    out = ctypes.c_void_p()
+    _check(_lib.hubbard_server_create(int(hbm_budget), int(max_slots), ctypes.byref(out)), "hubbard_server_create")
+    return Server(out.value)
+
+
+def hubbard_server_submit(srv: Server, sites, edges, n_up, n_dn, t=1.0, U=0.0, tol=1e-10, max_iter=300,
+                          precision=HUBBARD_MIXED, seed=DEFAULT_SEED, tag=0) -> int:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    r = hubbard_request(int(sites), e.ctypes.data, len(e), int(n_up), int(n_dn), float(t), float(U), float(tol),
+                        int(max_iter), int(precision), int(seed) & (2**64 - 1), int(tag) & (2**64 - 1))
+    rid = ctypes.c_uint64()
+    _check(_lib.hubbard_server_submit(srv, ctypes.byref(r), ctypes.byref(rid)), "hubbard_server_submit")
+    return rid.value
+
+
+def hubbard_server_poll(srv: Server, cap: int = 256, timeout_us: int = 0):
+    buf = (hubbard_completion * cap)()
+    n = ctypes.c_int()
+    _check(_lib.hubbard_server_poll(srv, buf, cap, ctypes.byref(n), int(timeout_us)), "hubbard_server_poll")
+    out = []
+    for k in range(n.value):
+        c = buf[k]
+        d = _result_dict(c.result, None)
+        # the completion's own status (a rejected request has an empty result)
+        d.update({"id": c.id, "tag": c.tag, "status": c.status, "t_submit": c.t_submit, "t_admit": c.t_admit,
+                  "t_start": c.t_start, "t_done": c.t_done})
+        out.append(d)
+    return out
+
+
+def hubbard_server_stats(srv: Server) -> dict:
+    st = hubbard_server_stats_t()
+    _check(_lib.hubbard_server_stats(srv, ctypes.byref(st)), "hubbard_server_stats")
+    return {name: getattr(st, name) for name, _ in hubbard_server_stats_t._fields_}
+
+
+def hubbard_server_destroy(srv: Server):
+    if srv.ptr:
+        _check(_lib.hubbard_server_destroy(ctypes.c_void_p(srv.ptr)), "hubbard_server_destroy")
+        srv.ptr = None
+
+
+def hubbard_admission_plan(footprints, budget: int, used: int, free_slots: int):
+    fp = np.ascontiguousarray(np.asarray(footprints, dtype=np.uint64))
+    take = np.zeros(len(fp), dtype=np.int32)
+    n = _lib.hubbard_admission_plan(fp.ctypes.data, len(fp), int(budget), int(used), int(free_slots),
+                                    take.ctypes.data)
+    if n < 0:
+        raise HubbardError(n, "hubbard_admission_plan", "")
+    return take.tolist()
+
+
 def sector_dim(sites: int, n_up: int, n_dn: int) -> int:
     return math.comb(sites, n_up) * math.comb(sites, n_dn)
 
 
 __all__ = [n for n in dir() if n.startswith("hubbard_") or n.startswith("HUBBARD_")] + [
-    "Handle", "HubbardError", "sector_dim", "LIB_PATH", "HEADER_PATH"]
+    "Handle", "Server", "HubbardError", "sector_dim", "LIB_PATH", "HEADER_PATH"]

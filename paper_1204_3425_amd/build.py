@@ -13,7 +13,7 @@ ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
-SOURCES = ["builder.cpp", "tridiag.cpp", "capi.cpp", "kernels.hip", "hv.hip"]
+SOURCES = ["builder.cpp", "tridiag.cpp", "capi.cpp", "kernels.hip", "hv.hip", "batch.hip", "batch.cpp", "server.cpp"]
 
 
 def build(verbose: bool = False) -> str:
@@ -21,7 +21,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

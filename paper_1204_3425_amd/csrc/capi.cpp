@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "internal.h"
 
 namespace hub {
@@ -96,7 +97,7 @@ static void free_device(hubbard *h)
 {
     DeviceTables &d = h->dev;
     void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
-                    d.dn_groups64, d.dn_groups32, d.dn_nq};
+                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.up_blk, d.up_nint, d.up_next, d.up_bstart};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -112,6 +113,73 @@ static T *upload(const void *src, size_t bytes, size_t &total)
         HUB_HIP(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
     total += bytes;
     return static_cast<T *>(p);
+}
+
+// Blocks of up configurations for the blocked slab pass: the largest number p
+// of low sites such that rows sharing the occupation of sites p.. form blocks
+// of at most kMaxBlockRows rows (configurations in ascending order keep each
+// block contiguous).
+constexpr int kMaxBlockRows = 1024;
+
+static void upload_blocked_up(hubbard *h, size_t &total)
+{
+    DeviceTables &d = h->dev;
+    const SpinTable &up = h->up;
+    const int64_t du = up.dim;
+    std::vector<int32_t> bstart;
+    for (int p = h->sites; p >= 0; p--) {
+        bstart.assign(1, 0);
+        int64_t longest = 0, run = 1;
+        auto key = [&](int64_t r) { return p >= 32 ? 0u : up.states[(size_t)r] >> p; };
+        for (int64_t r = 1; r < du; r++) {
+            if (key(r) != key(r - 1)) {
+                bstart.push_back((int32_t)r);
+                longest = std::max(longest, run);
+                run = 1;
+            } else {
+                run++;
+            }
+        }
+        longest = std::max(longest, run);
+        bstart.push_back((int32_t)du);
+        if (longest <= kMaxBlockRows)
+            break;
+    }
+    const int nb = (int)bstart.size() - 1;
+    std::vector<int32_t> blk_of((size_t)du);
+    int longest = 0;
+    for (int b = 0; b < nb; b++) {
+        longest = std::max(longest, bstart[(size_t)b + 1] - bstart[(size_t)b]);
+        for (int32_t r = bstart[(size_t)b]; r < bstart[(size_t)b + 1]; r++)
+            blk_of[(size_t)r] = b;
+    }
+    const int w = std::max(1, up.width);
+    std::vector<uint32_t> ent((size_t)du * (size_t)w, 0u);
+    std::vector<uint16_t> nint((size_t)du), next((size_t)du);
+    for (int64_t r = 0; r < du; r++) {
+        const int b = blk_of[(size_t)r];
+        size_t o = (size_t)r * (size_t)w;
+        int ni = 0, ne = 0;
+        for (int pass = 0; pass < 2; pass++)
+            for (int k = 0; k < up.row_nnz[(size_t)r]; k++) {
+                const size_t src = (size_t)k * (size_t)du + (size_t)r;
+                const int32_t c = up.col[src];
+                const bool inside = blk_of[(size_t)c] == b;
+                if (inside != (pass == 0))
+                    continue;
+                const uint32_t sg = up.sgn[src] < 0 ? 0x80000000u : 0u;
+                ent[o++] = (uint32_t)(inside ? c - bstart[(size_t)b] : c) | sg;
+                (inside ? ni : ne)++;
+            }
+        nint[(size_t)r] = (uint16_t)ni;
+        next[(size_t)r] = (uint16_t)ne;
+    }
+    d.up_blk = upload<uint32_t>(ent.data(), ent.size() * 4, total);
+    d.up_nint = upload<uint16_t>(nint.data(), nint.size() * 2, total);
+    d.up_next = upload<uint16_t>(next.data(), next.size() * 2, total);
+    d.up_bstart = upload<int32_t>(bstart.data(), bstart.size() * 4, total);
+    d.up_nblocks = nb;
+    d.up_max_block = longest;
 }
 
 static void upload_tables(hubbard *h)
@@ -161,6 +229,7 @@ static void upload_tables(hubbard *h)
         (es == 8 ? d.dn_groups64 : d.dn_groups32) = dev;
     }
     d.dn_nq = upload<uint8_t>(nq.data(), nq.size(), total);
+    upload_blocked_up(h, total);
     d.bytes = total;
 }
 
@@ -177,6 +246,12 @@ static HvArgs hv_args(const hubbard *h)
     a.dn_groups32 = reinterpret_cast<const uint4 *>(h->dev.dn_groups32);
     a.dn_nq = h->dev.dn_nq;
     a.dn_ngroups = h->dev.dn_ngroups;
+    a.up_blk = h->dev.up_blk;
+    a.up_nint = h->dev.up_nint;
+    a.up_next = h->dev.up_next;
+    a.up_bstart = h->dev.up_bstart;
+    a.up_nblocks = h->dev.up_nblocks;
+    a.up_max_block = h->dev.up_max_block;
     a.dim_up = h->up.dim;
     a.dim_dn = h->dn.dim;
     a.w_up = h->up.width;
@@ -209,6 +284,9 @@ struct LanczosOut {
     double seconds_first = 0;
 };
 
+// sectors from this size on take the fused Lanczos step
+constexpr int64_t kFusedMinDim = 1 << 16;
+
 template <typename T>
 static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
 {
@@ -227,7 +305,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     // the FP64 scratch of the residual (2 * npad * sizeof(T) >= npad * 8 bytes)
     DevBuf work(2 * sizeof(T) * (size_t)npad);
     T *vecs[2] = {work.as<T>(), work.as<T>() + npad};
-    DevBuf partials(sizeof(double) * (size_t)(2 * std::max(std::max(hb, plan64.nparts), sb) + 64));
+    DevBuf partials(sizeof(double) * (size_t)(3 * std::max(std::max(hb, plan64.nparts), sb) + 64));
     DevBuf scal(sizeof(double) * 8 + sizeof(double) * 2 * (size_t)(max_iter + 1));
     double *S = scal.as<double>();
     double *hist = S + 8;
@@ -249,12 +327,27 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
         launch_start_fill<T>(given, seed, inv_norm, C, P, h->up.dim, h->dn.dim, ld, s);
         launch_init_scalars(S, s);
     };
-    auto step = [&](T *C, T *P, int j0) {
-        launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, HV_LANCZOS, 0.0, S + 1, partials.as<double>(), s);
-        launch_reduce_step(partials.as<double>(), hb, RED_DOT, S, hist, j0, s);
+    // Fused form (two-pass plans of large sectors): the update q - a_j f_j
+    // is not a pass of its own.  The step leaves q = H v_j - b_j v_{j-1} in P,
+    // the next step's row pass forms f_{j+1} from it while staging rows, and
+    // b_{j+1} comes from the expanded norm (the reduction's RED_FUSED mode).
+    // Small sectors, where a breakdown or an exhausted space is near, keep the
+    // update pass and the norm of the stored vector.
+    const bool fused = plan.two_pass && plan.blk_grid > 0 && n >= kFusedMinDim;
+    auto hv_step = [&](T *C, T *P) {
+        return launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, fused ? HV_FUSED : HV_LANCZOS, 0.0,
+                             fused ? S : S + 1, partials.as<double>(), s);
+    };
+    auto finish_step = [&](T *C, T *P, int np, int j0) {
+        if (fused) {
+            launch_reduce_step(partials.as<double>(), np, RED_FUSED, S, hist, j0, s);
+            return;
+        }
+        launch_reduce_step(partials.as<double>(), np, RED_DOT, S, hist, j0, s);
         launch_axpy_norm<T>(P, C, S + 3, npad, partials.as<double>(), sb, s);
         launch_reduce_step(partials.as<double>(), sb, RED_NORM, S, hist, j0, s);
     };
+    auto step = [&](T *C, T *P, int j0) { finish_step(C, P, hv_step(C, P), j0); };
 
     // ---- first pass: run ahead of the host by `lookahead` steps
     const int lookahead = n >= (int64_t)4000000 ? 2 : 8;
@@ -341,6 +434,14 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     start_pass(bufs[0], bufs[1]);
     for (int j0 = 0; j0 < m; j0++) {
         T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
+        if (fused) {
+            // f_j exists once the step's row pass has formed it; S[0] still holds 1/s_j
+            const int np = hv_step(C, P);
+            launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, h->up.dim, h->dn.dim, ld, j0 == 0, s);
+            if (j0 + 1 < m)
+                finish_step(C, P, np, j0);
+            continue;
+        }
         launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, h->up.dim, h->dn.dim, ld, j0 == 0, s);
         if (j0 + 1 < m)
             step(C, P, j0);
@@ -355,9 +456,8 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
         c = -c;
     launch_scale(o.psi, c, n, s);
     // FP64 residual |H psi - E0 psi| and Rayleigh quotient <psi|H|psi>
-    const int hb64 = plan64.nparts;
-    launch_hv2<double>(args, plan64, o.psi, h->dn.dim, nullptr, 0, work.as<double>(), ld, HV_RESIDUAL, out.e0, nullptr,
-                       partials.as<double>(), s);
+    const int hb64 = launch_hv2<double>(args, plan64, o.psi, h->dn.dim, nullptr, 0, work.as<double>(), ld, HV_RESIDUAL,
+                                        out.e0, nullptr, partials.as<double>(), s);
     launch_reduce(partials.as<double>(), hb64, hb64, 2, S + 4, s);
     HUB_HIP(hipMemcpyAsync(hh, S + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HUB_HIP(hipStreamSynchronize(s));
@@ -365,7 +465,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     out.rayleigh = hh[1];
 }
 
-static void validate_opts(const hubbard_opts &o)
+void validate_opts(const hubbard_opts &o)
 {
     if (!(o.max_iter >= 1))
         fail(HUBBARD_EINVAL, "max_iter must be >= 1");
@@ -375,7 +475,7 @@ static void validate_opts(const hubbard_opts &o)
         fail(HUBBARD_EINVAL, "unknown precision");
 }
 
-static int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res)
+int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res)
 {
     validate_opts(o);
     use_device(h);
@@ -399,7 +499,14 @@ static int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res)
         r.e0 = out.e0;
         r.residual = o.psi ? out.residual : -1.0;
         r.rayleigh = o.psi ? out.rayleigh : NAN;
-        r.err_est = o.psi ? out.residual / std::fmax(1.0, std::fabs(out.e0)) : -1.0;
+        if (o.psi) {
+            r.err_est = out.residual / std::fmax(1.0, std::fabs(out.e0));
+        } else {
+            // Lanczos estimate of |H psi - E0 psi| for the Ritz pair: b_{m+1} |y_m|
+            std::vector<double> y((size_t)out.m);
+            tridiag_lowest_vector(out.a.data(), out.b.data(), out.m, out.e0, y.data());
+            r.err_est = std::fabs(out.b.back() * y.back()) / std::fmax(1.0, std::fabs(out.e0));
+        }
         r.seconds = std::chrono::duration<double>(t1 - t0).count();
         r.seconds_per_iter = out.m ? out.seconds_first / out.m : 0.0;
         r.n_iter = out.m;
@@ -674,12 +781,37 @@ int hubbard_lanczos_batch(hubbard_h *hs, int n, const hubbard_opts *opts, hubbar
     return guarded([&]() -> int {
         if (n < 0 || (n > 0 && (!hs || !opts || !res)))
             fail(HUBBARD_EINVAL, "bad batch arguments");
-        int worst = HUBBARD_OK;
+        // small sectors without a psi request share launches; the rest run one by one
+        std::vector<hubbard *> bh;
+        std::vector<hubbard_opts> bo;
+        std::vector<int> bidx;
         for (int i = 0; i < n; i++) {
             check_handle(hs[i]);
-            int rc = lanczos_impl(hs[i], opts[i], &res[i]);
+            validate_opts(opts[i]);
+            if (!opts[i].psi && batchable(hs[i], opts[i].precision)) {
+                bh.push_back(hs[i]);
+                bo.push_back(opts[i]);
+                bidx.push_back(i);
+            }
+        }
+        int worst = HUBBARD_OK;
+        auto note = [&](int rc) {
             if (rc != HUBBARD_OK && (worst == HUBBARD_OK || rc < worst))
                 worst = rc;
+        };
+        if (!bh.empty()) {
+            use_device(bh[0]);
+            std::vector<hubbard_result> br(bh.size());
+            run_batch(bh.data(), bo.data(), br.data(), (int)bh.size(), bh[0]->stream);
+            for (size_t k = 0; k < bidx.size(); k++) {
+                res[bidx[k]] = br[k];
+                note(br[k].status);
+            }
+        }
+        for (int i = 0; i < n; i++) {
+            if (!opts[i].psi && batchable(hs[i], opts[i].precision))
+                continue;
+            note(lanczos_impl(hs[i], opts[i], &res[i]));
         }
         return worst;
     });

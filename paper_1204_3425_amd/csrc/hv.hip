@@ -89,19 +89,32 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
+    double cshift = 0.0;
     if (MODE == HV_LANCZOS) {
         alpha = coef[0];
         beta = coef[1];
+    } else if (MODE == HV_FUSED) {
+        alpha = coef[1];
+        beta = coef[2];
+        cshift = coef[3];
     }
     const int64_t ddn = p.dim_dn;
     const int64_t slot = ddn + 1;  // staged row length including the zero slot
-    const T mt = (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta;
+    const T mt = (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta, c_s = (T)cshift;
 
     for (int64_t r0 = (int64_t)blockIdx.x * RPB; r0 < p.dim_up; r0 += (int64_t)gridDim.x * RPB) {
         const int nr = (int)min((int64_t)RPB, p.dim_up - r0);
         for (int64_t i = threadIdx.x; i < ddn * nr; i += blockDim.x) {
             const int64_t q = i / ddn, d = i - q * ddn;
-            xs[q * slot + d] = x[(r0 + q) * ldx + d];
+            if (MODE == HV_FUSED) {
+                // the q - a_j f_j update of the previous step, formed here and kept
+                T *xp = const_cast<T *>(x) + (r0 + q) * ldx + d;
+                const T v = *xp - c_s * y[(r0 + q) * ldy + d];
+                *xp = v;
+                xs[q * slot + d] = v;
+            } else {
+                xs[q * slot + d] = x[(r0 + q) * ldx + d];
+            }
         }
         if (threadIdx.x < RPB)
             xs[threadIdx.x * slot + ddn] = (T)0;
@@ -154,7 +167,7 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                         T *yp = y + (r0 + q) * ldy + d;
                         if (MODE == HV_STORE)
                             *yp = hx;
-                        else if (MODE == HV_LANCZOS)
+                        else if (MODE == HV_LANCZOS || MODE == HV_FUSED)
                             *yp = a_s * hx + b_s * *yp;
                         else
                             *yp = hx - a_s * xv;
@@ -261,6 +274,183 @@ __global__ __launch_bounds__(kSlabThreads) void hv_slabs_kernel(SlabArgs p, cons
     }
 }
 
+
+struct BlockArgs {
+    const uint32_t *__restrict__ ent;    // per row: block-local internal hops, then external rows
+    const uint16_t *__restrict__ nint;
+    const uint16_t *__restrict__ next;
+    const int32_t *__restrict__ bstart;
+    int64_t dim_up, dim_dn;
+    int w_up, nblocks, nslab;
+    double t;
+};
+
+// Blocked slab pass.  Workgroup b works on slab s and row block k, with
+// xcd = b mod 8, s = (b / 8 / nblocks) * 8 + xcd, k = (b / 8) mod nblocks: the
+// dispatcher starts workgroups in index order, so each XCD moves through its
+// slabs about one at a time and the rows that other blocks' hops re-read are
+// still in that XCD's L2.  A slab is 128 bytes of every row (one cache line).
+// The workgroup stages its block's slab segment in LDS; hops that stay inside
+// the block read LDS, the others read global memory.  Eight lanes cover one
+// 128-byte row segment with 16-byte accesses, so a wave updates eight rows.
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *__restrict__ x, int64_t ldx,
+                                                         T *__restrict__ y, int64_t ldy, double alpha,
+                                                         const double *__restrict__ coef,
+                                                         double *__restrict__ partials)
+{
+    constexpr int EPL = 16 / (int)sizeof(T);  // elements per lane
+    constexpr int SL = 8 * EPL;               // slab width in elements
+    typedef __attribute__((ext_vector_type(EPL))) T vec;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    vec *xs = reinterpret_cast<vec *>(smem_raw);  // [row in block][8]
+    // 16-byte load of row elements d..d+EPL-1; past the last column the
+    // elements are read one by one (and read as zero), so no access leaves the row
+    auto load_row = [&](const T *row, int64_t d) -> vec {
+        if (d + EPL <= p.dim_dn)
+            return *reinterpret_cast<const vec *>(row + d);
+        vec v;
+#pragma unroll
+        for (int e = 0; e < EPL; e++)
+            v[e] = d + e < p.dim_dn ? row[d + e] : (T)0;
+        return v;
+    };
+    __shared__ double red[16];
+    if (MODE == HV_LANCZOS)
+        alpha = coef[0];
+    else if (MODE == HV_FUSED)
+        alpha = coef[1];
+    const T a_s = (T)alpha, tp = (T)p.t, tm = (T)(-p.t);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwave = blockDim.x >> 6;
+    const int xcd = blockIdx.x & 7;
+    const int local = blockIdx.x >> 3;
+    const int s = (local / p.nblocks) * 8 + xcd;
+    const int blk = local % p.nblocks;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    if (s < p.nslab) {
+        const int64_t b0 = p.bstart[blk];
+        const int bs = p.bstart[blk + 1] - (int)b0;
+        const int64_t d0 = (int64_t)s * SL;
+        for (int i = threadIdx.x; i < bs * 8; i += blockDim.x) {
+            const int rr = i >> 3, q = i & 7;
+            xs[i] = load_row(x + (b0 + rr) * ldx, d0 + q * EPL);
+        }
+        __syncthreads();
+        const int sub = lane >> 3, q = lane & 7;
+        const int64_t d = d0 + q * EPL;
+        for (int rb = wave * 8; rb < bs; rb += nwave * 8) {
+            const int rl = min(rb + sub, bs - 1);
+            const bool okr = rb + sub < bs;
+            const int64_t r = b0 + rl;
+            const uint32_t *__restrict__ er = p.ent + r * p.w_up;
+            const int ni = p.nint[r], ne = p.next[r];
+            int nim = ni, nem = ne;
+            for (int o = 8; o < 64; o <<= 1) {
+                nim = max(nim, __shfl_xor(nim, o, 64));
+                nem = max(nem, __shfl_xor(nem, o, 64));
+            }
+            vec acc = (vec)(T)0;
+            for (int k0 = 0; k0 < nim; k0 += 8) {
+                int li[8];
+                T cf[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const bool live = k0 + u < ni;
+                    const uint32_t e = er[live ? k0 + u : 0];
+                    li[u] = live ? (int)(e & 0x7fffffffu) : rl;
+                    cf[u] = live ? ((e >> 31) ? tp : tm) : (T)0;
+                }
+                vec v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    v[u] = xs[li[u] * 8 + q];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    acc += cf[u] * v[u];
+            }
+            for (int k0 = 0; k0 < nem; k0 += 8) {
+                int64_t off[8];
+                T cf[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const bool live = k0 + u < ne;
+                    const uint32_t e = er[live ? ni + k0 + u : 0];
+                    off[u] = (live ? (int64_t)(e & 0x7fffffffu) : r) * ldx;
+                    cf[u] = live ? ((e >> 31) ? tp : tm) : (T)0;
+                }
+                vec v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    v[u] = load_row(x + off[u], d);
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    acc += cf[u] * v[u];
+            }
+            if (okr && d < p.dim_dn) {
+                T *yp = y + r * ldy + d;
+                const vec xv = xs[rl * 8 + q];
+                const bool whole = d + EPL <= p.dim_dn;
+                vec prev;
+                if (whole) {
+                    prev = __builtin_nontemporal_load(reinterpret_cast<const vec *>(yp));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < EPL; e++)
+                        prev[e] = d + e < p.dim_dn ? yp[e] : (T)0;
+                }
+                vec out;
+                if (MODE == HV_STORE)
+                    out = prev + acc;
+                else if (MODE == HV_LANCZOS || MODE == HV_FUSED)
+                    out = prev + a_s * acc;
+                else
+                    out = prev + acc;  // H x - alpha x
+#pragma unroll
+                for (int e = 0; e < EPL; e++) {
+                    if (d + e < p.dim_dn) {
+                        if (MODE == HV_LANCZOS) {
+                            acc0 += (double)out[e] * (double)xv[e];
+                        } else if (MODE == HV_FUSED) {
+                            acc0 += (double)out[e] * (double)xv[e];
+                            acc1 += (double)out[e] * (double)out[e];
+                            acc2 += (double)xv[e] * (double)xv[e];
+                        } else if (MODE == HV_RESIDUAL) {
+                            acc0 += (double)out[e] * (double)out[e];
+                            acc1 += (double)xv[e] * ((double)out[e] + alpha * (double)xv[e]);
+                        }
+                    }
+                }
+                if (MODE != HV_RESIDUAL) {
+                    if (whole) {
+                        __builtin_nontemporal_store(out, reinterpret_cast<vec *>(yp));
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < EPL; e++)
+                            if (d + e < p.dim_dn)
+                                yp[e] = out[e];
+                    }
+                }
+            }
+        }
+    }
+    if (MODE != HV_STORE) {
+        const double s0 = block_sum2(acc0, red);
+        if (threadIdx.x == 0)
+            partials[blockIdx.x] = s0;
+        if (MODE == HV_RESIDUAL || MODE == HV_FUSED) {
+            const double s1 = block_sum2(acc1, red);
+            if (threadIdx.x == 0)
+                partials[gridDim.x + blockIdx.x] = s1;
+        }
+        if (MODE == HV_FUSED) {
+            const double s2 = block_sum2(acc2, red);
+            if (threadIdx.x == 0)
+                partials[2 * gridDim.x + blockIdx.x] = s2;
+        }
+    }
+}
+
 template <typename T, int RPB>
 size_t row_lds(int64_t ddn)
 {
@@ -308,6 +498,17 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
     pl.slab_lds = (size_t)pl.slab_rw * (size_t)(wup * 4 + 4);
     pl.nslab = (int)((ddn + kSlab - 1) / kSlab);
     pl.nparts = pl.slab_grid;
+    // blocked slab pass: 128-byte slabs, one workgroup per (slab, row block)
+    if (a.up_nblocks > 0 && a.up_max_block > 0) {
+        const int sl = 128 / elem_bytes;
+        pl.blk_nslab = (int)((ddn + sl - 1) / sl);
+        const int64_t per_xcd = (pl.blk_nslab + 7) / 8;
+        pl.blk_grid = (int)(8 * per_xcd * a.up_nblocks);
+        pl.blk_lds = (size_t)a.up_max_block * 128;
+        const int64_t thr = ((int64_t)a.up_max_block * 8 + 63) / 64 * 64;
+        pl.blk_threads = (int)(thr < 1024 ? (thr < 256 ? 256 : thr) : 1024);
+        pl.nparts = std::max(pl.nparts, pl.blk_grid);
+    }
     return pl;
 }
 
@@ -326,13 +527,15 @@ static void launch_rows_rpb(const RowArgs &ra, const HvPlan &pl, const T *x, int
         go(hv_rows_kernel<T, RPB, HV_STORE>);
     else if (mode == HV_LANCZOS)
         go(hv_rows_kernel<T, RPB, HV_LANCZOS>);
+    else if (mode == HV_FUSED)
+        go(hv_rows_kernel<T, RPB, HV_FUSED>);
     else
         go(hv_rows_kernel<T, RPB, HV_RESIDUAL>);
 }
 
 template <typename T>
-void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
-                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s)
+int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
+               int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s)
 {
     if (!pl.two_pass) {
         // rows too wide for LDS: the one-pass kernel (dense rows only)
@@ -340,7 +543,7 @@ void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y
             launch_hv<T>(a, x, nullptr, HV_RESIDUAL, alpha, coef, partials, pl.nparts, s);
         else
             launch_hv<T>(a, x, y, mode, alpha, coef, partials, pl.nparts, s);
-        return;
+        return pl.nparts;
     }
     RowArgs ra;
     ra.groups = sizeof(T) == 8 ? a.dn_groups64 : a.dn_groups32;
@@ -360,6 +563,40 @@ void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y
         launch_rows_rpb<T, 2>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else
         launch_rows_rpb<T, 1>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+
+    const int64_t slw = 128 / (int64_t)sizeof(T);
+    if (pl.blk_grid > 0 && ldx % slw == 0 && ldyr % slw == 0) {
+        BlockArgs ba;
+        ba.ent = a.up_blk;
+        ba.nint = a.up_nint;
+        ba.next = a.up_next;
+        ba.bstart = a.up_bstart;
+        ba.dim_up = a.dim_up;
+        ba.dim_dn = a.dim_dn;
+        ba.w_up = a.w_up > 0 ? a.w_up : 1;
+        ba.nblocks = a.up_nblocks;
+        ba.nslab = pl.blk_nslab;
+        ba.t = a.t;
+        auto gob = [&](auto kern) {
+            if (pl.blk_lds > 64 * 1024)
+                HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)pl.blk_lds));
+            hipLaunchKernelGGL(kern, dim3(pl.blk_grid), dim3(pl.blk_threads), pl.blk_lds, s, ba, x, ldx, yr, ldyr,
+                               alpha, coef, partials);
+            HUB_HIP(hipGetLastError());
+        };
+        if (mode == HV_STORE)
+            gob(hv_blocks_kernel<T, HV_STORE>);
+        else if (mode == HV_LANCZOS)
+            gob(hv_blocks_kernel<T, HV_LANCZOS>);
+        else if (mode == HV_FUSED)
+            gob(hv_blocks_kernel<T, HV_FUSED>);
+        else
+            gob(hv_blocks_kernel<T, HV_RESIDUAL>);
+        return pl.blk_grid;
+    }
+    if (mode == HV_FUSED)
+        fail(HUBBARD_EDEVICE, "fused Lanczos step needs rows aligned to 128 bytes");
 
     SlabArgs sa;
     sa.up_rows = a.up_rows;
@@ -384,11 +621,12 @@ void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y
         go(hv_slabs_kernel<T, HV_LANCZOS>);
     else
         go(hv_slabs_kernel<T, HV_RESIDUAL>);
+    return pl.slab_grid;
 }
 
-template void launch_hv2<double>(const HvArgs &, const HvPlan &, const double *, int64_t, double *, int64_t,
-                                 double *, int64_t, int, double, const double *, double *, hipStream_t);
-template void launch_hv2<float>(const HvArgs &, const HvPlan &, const float *, int64_t, float *, int64_t, float *,
+template int launch_hv2<double>(const HvArgs &, const HvPlan &, const double *, int64_t, double *, int64_t, double *,
                                 int64_t, int, double, const double *, double *, hipStream_t);
+template int launch_hv2<float>(const HvArgs &, const HvPlan &, const float *, int64_t, float *, int64_t, float *,
+                               int64_t, int, double, const double *, double *, hipStream_t);
 
 }  // namespace hub

@@ -48,6 +48,13 @@ struct DeviceTables {
     uint32_t *dn_groups64 = nullptr, *dn_groups32 = nullptr;
     uint8_t *dn_nq = nullptr;      // groups needed by the 64 columns of a wave
     int dn_ngroups = 0;
+    // up table for the blocked slab pass: rows are grouped in blocks of equal
+    // occupation of the top sites; per row the hops that stay in the block come
+    // first (block-local row | sign<<31), then the others (row | sign<<31)
+    uint32_t *up_blk = nullptr;
+    uint16_t *up_nint = nullptr, *up_next = nullptr;
+    int32_t *up_bstart = nullptr;  // nblocks + 1 row offsets
+    int up_nblocks = 0, up_max_block = 0;
     size_t bytes = 0;
 };
 
@@ -68,6 +75,10 @@ struct hubbard {
 
 namespace hub {
 
+// capi.cpp: the single-instance Lanczos driver (throws hub::Error)
+void validate_opts(const hubbard_opts &o);
+int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res);
+
 // builder.cpp
 void build_spin_table(int sites, const std::vector<int32_t> &edges, int n, SpinTable &out);
 uint64_t binomial(int n, int k);
@@ -84,6 +95,10 @@ struct HvArgs {
     const uint4 *dn_groups64, *dn_groups32;
     const uint8_t *dn_nq;
     int dn_ngroups;
+    const uint32_t *up_blk;
+    const uint16_t *up_nint, *up_next;
+    const int32_t *up_bstart;
+    int up_nblocks, up_max_block;
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
     double t, U;
@@ -98,16 +113,21 @@ struct HvPlan {
     size_t rows_lds = 0;
     int slab_rw = 1, slab_grid = 8, nslab = 1;
     size_t slab_lds = 0;
-    int nparts = 1;         // partial sums written per reduction
+    int blk_grid = 0, blk_nslab = 0, blk_threads = 1024;  // blocked slab pass (0: not available)
+    size_t blk_lds = 0;
+    int nparts = 1;         // largest number of partial sums any launch writes
 };
-enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2 };
-enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2 };
+enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2, HV_FUSED = 3 };
+enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2, RED_FUSED = 3 };
 
 // HV_STORE:    y = H x
 // HV_LANCZOS:  y = alpha H x + beta y (in place), alpha = coef[0], beta = coef[1];
 //              partials[b] = block b's share of y.x
 // HV_RESIDUAL: nothing stored; partials[b] = share of |Hx - alpha x|^2,
 //              partials[nblocks + b] = share of x.Hx
+// HV_FUSED:    (two-pass plans, padded rows) x <- x - c y is formed and written
+//              back first, then y = alpha H x + beta y; coef = S (S[1] alpha,
+//              S[2] beta, S[3] c); partials [3][n] = shares of y.x, y.y, x.x
 template <typename T>
 void launch_hv(const HvArgs &a, const T *x, T *y, int mode, double alpha, const double *coef, double *partials,
                int nblocks, hipStream_t s);
@@ -117,9 +137,10 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes);
 // x, y (and scratch) are row-major dim_up x dim_dn with row strides ldx, ldy
 // (lds_); scratch (the row-pass output) is used by HV_RESIDUAL only, where y
 // is not written.  Partial sums: pl.nparts values (HV_RESIDUAL: twice that).
+// Returns the number of partial sums written (HV_RESIDUAL: twice that many values).
 template <typename T>
-void launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
-                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s);
+int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
+               int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s);
 
 template <typename T>
 void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);

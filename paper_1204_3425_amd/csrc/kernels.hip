@@ -415,6 +415,13 @@ void launch_scale(double *v, double c, int64_t n, hipStream_t s)
 // mode RED_NORM (after that update): b_{j+1} = sqrt(sum); hist[2j+1] = b_{j+1};
 //   the roles of the two vectors swap, so the next H.v gets
 //   alpha = 1/b_{j+1}, beta = -b_{j+1} * S[0] (old 1/s), and S[0] = 1/b_{j+1}.
+// mode RED_FUSED (after a fused step, partials [3][n] = shares of y.x, y.y,
+//   x.x with x = X_j, the stored vector of norm s, and y = H X_j / s - b_j v_{j-1}):
+//   a_j = (y.x) / s, c = a_j / s, and the norm of the next vector
+//   X_{j+1} = y - c X_j, which the next step forms, is expanded as
+//   |y|^2 - 2 c (y.x) + c^2 |X_j|^2.  The expansion loses the digits of b_{j+1}
+//   that cancel against |y|; below 64 eps |y|^2 the subspace is taken as
+//   invariant (b_{j+1} = 0, a breakdown).
 // S = device scalars {1/s of the current vector, alpha, beta, c}.
 __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__ partials, int n, int stride,
                                                       double *__restrict__ out, int mode, double *__restrict__ S,
@@ -426,6 +433,28 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         acc += src[i];
     double s = block_sum(acc, red);
+    if (mode == RED_FUSED) {
+        double acc1 = 0.0, acc2 = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            acc1 += src[n + i];
+            acc2 += src[2 * n + i];
+        }
+        const double qq = block_sum(acc1, red);
+        const double xx = block_sum(acc2, red);
+        if (threadIdx.x == 0) {
+            const double a = s * S[0];
+            const double c = a * S[0];
+            const double b2 = qq - 2.0 * c * s + c * c * xx;
+            const double b = b2 > 64.0 * 0x1p-52 * qq ? sqrt(b2) : 0.0;
+            hist[2 * j] = a;
+            hist[2 * j + 1] = b;
+            S[3] = c;
+            S[2] = -b * S[0];
+            S[0] = b > 0.0 ? 1.0 / b : 0.0;
+            S[1] = S[0];
+        }
+        return;
+    }
     if (threadIdx.x == 0) {
         if (mode == RED_PLAIN) {
             out[blockIdx.x] = s;

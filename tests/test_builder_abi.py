@@ -170,3 +170,22 @@ def test_apply_ld_validates_strides_before_touching_the_device():
     assert lib.hubbard_apply_ld(h.ptr, 4096, h.dim_dn, 4096 + 8, h.dim_dn) == hb.HUBBARD_EINVAL
     info = hb.hubbard_info(h)
     assert info["ld_pref"] >= h.dim_dn and info["ld_pref"] % 64 == 0
+
+
+def test_admission_plan_first_fit():
+    """The server's admission rule: first fit in arrival order under the budget
+    and the free slots."""
+    assert hb.hubbard_admission_plan([10, 20, 30], 100, 0, 8) == [1, 1, 1]
+    assert hb.hubbard_admission_plan([10, 20, 30], 100, 50, 8) == [1, 1, 0]
+    # a request that does not fit does not block smaller ones behind it
+    assert hb.hubbard_admission_plan([60, 30, 10], 100, 50, 8) == [0, 1, 1]
+    assert hb.hubbard_admission_plan([10, 10, 10], 100, 0, 2) == [1, 1, 0]
+    assert hb.hubbard_admission_plan([10], 100, 200, 4) == [0]
+    assert hb.hubbard_admission_plan([], 100, 0, 4) == []
+    # never over the budget, whatever the mix
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        fp = rng.integers(1, 50, size=12)
+        used = int(rng.integers(0, 100))
+        take = hb.hubbard_admission_plan(fp, 100, used, int(rng.integers(0, 6)))
+        assert used + sum(f for f, t in zip(fp, take) if t) <= max(100, used)

@@ -274,6 +274,48 @@ def test_lanczos_4x4_against_golden():
     assert mix["E0"] == pytest.approx(g["E0"], rel=1e-6)
 
 
+def test_lanczos_large_sector_matches_oracle():
+    """A 392,040-state sector: large enough for the fused step (the update
+    q - a_j f_j formed inside the next H.v, b_{j+1} from the expanded norm),
+    small enough for the oracle to follow with psi."""
+    p = workload.problem("torus3x4_4u5d", 12, workload.torus(3, 4), 4, 5, 1.0, 6.0)
+    h = _build(p)
+    m = _oracle(p)
+    _say("oracle lanczos", p.name, p.dim)
+    ref = m.lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300, want_psi=True)
+    for prec in (hb.HUBBARD_FP64, hb.HUBBARD_MIXED):
+        _say("lanczos", p.name, prec)
+        got = _lanczos_gpu(h, p, prec, 1e-12 if prec == hb.HUBBARD_FP64 else 1e-9, 300, want_psi=True)
+        if prec == hb.HUBBARD_FP64:
+            assert got["E0"] == pytest.approx(ref["E0"], rel=1e-10)
+            assert np.allclose(got["a"][:20], ref["a"][:20], rtol=1e-12, atol=1e-13)
+            assert np.allclose(got["b"][:20], ref["b"][:20], rtol=1e-12, atol=1e-13)
+            assert abs(got["psi"] @ ref["psi"]) > 1 - 1e-8
+            assert got["rayleigh"] == pytest.approx(ref["E0"], rel=1e-11)
+        else:
+            assert got["E0"] == pytest.approx(ref["E0"], rel=1e-6)
+            assert abs(got["psi"] @ ref["psi"]) > 1 - 1e-4
+        assert got["residual"] == pytest.approx(
+            np.linalg.norm(m.apply(got["psi"]) - got["E0"] * got["psi"]), rel=1e-6, abs=1e-12)
+
+
+def test_lanczos_large_sector_breakdown():
+    """Atomic limit (t = 0) of a fused-size sector from a start vector in the
+    span of two basis states: the Krylov space is that plane, the run stops
+    with a breakdown after two steps, and E0 is the lower diagonal element."""
+    p = workload.problem("torus3x4_atomic", 12, workload.torus(3, 4), 4, 5, 0.0, 4.0)
+    h = _build(p)
+    diag = _oracle(p).diagonal()
+    J = 0
+    K = int(np.flatnonzero(diag != diag[J])[0])
+    f = np.zeros(p.dim)
+    f[J] = f[K] = 1.0 / math.sqrt(2.0)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 50, want_psi=True, start=torch.from_numpy(f).to(DEV))
+    assert got["stop"] == "breakdown" and got["n_iter"] == 2
+    assert got["E0"] == pytest.approx(min(diag[J], diag[K]), rel=1e-12, abs=1e-12)
+    assert got["residual"] < 1e-10
+
+
 def test_lanczos_is_deterministic():
     p = workload.problem("torus3x4", 12, workload.torus(3, 4), 4, 5, 1.0, 6.0)
     h = _build(p)
@@ -301,14 +343,65 @@ def test_lanczos_degenerate_sectors(p):
         assert got["E0"] == pytest.approx(2 - math.sqrt(4 + 4), rel=1e-12)
 
 
-def test_batch_equals_alone():
-    probs = workload.batch64(6)
+_ORACLE_E0 = {}
+
+
+def _oracle_run(p):
+    """Oracle Lanczos from the problem's seed, cached per problem."""
+    if p not in _ORACLE_E0:
+        _ORACLE_E0[p] = _oracle(p).lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300)
+    return _ORACLE_E0[p]
+
+
+def _batch(handles, probs, precision, tol=1e-10, max_iter=300, psis=None):
+    r = hb.hubbard_lanczos_batch(handles, tol=tol, max_iter=max_iter, precision=precision,
+                                 seeds=[p.seed for p in probs], psis=psis, history=True)
+    torch.cuda.synchronize()
+    return r
+
+
+@pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
+def test_batch_matches_oracle_and_solo(precision):
+    """Batched solves (shared launches) against the oracle and against the
+    single-instance path."""
+    probs = workload.batch64(8)
     hs = [_build(p) for p in probs]
-    alone = [_lanczos_gpu(h, p, hb.HUBBARD_MIXED, 1e-10, 300) for h, p in zip(hs, probs)]
-    batch = hb.hubbard_lanczos_batch(hs, tol=1e-10, max_iter=300, precision=hb.HUBBARD_MIXED,
-                                     seeds=[p.seed for p in probs], history=True)
-    for a, b, p in zip(alone, batch, probs):
-        assert b["E0"] == pytest.approx(a["E0"], rel=1e-12), p.name
-        m = _oracle(p)
-        ref = m.lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300)
-        assert b["E0"] == pytest.approx(ref["E0"], rel=1e-6), p.name
+    _say("batch of", len(probs), "precision", precision)
+    # the oracle runs stop at an energy change of 1e-12; the FP64 runs use the same test
+    tol = 1e-12 if precision == hb.HUBBARD_FP64 else 1e-10
+    got = _batch(hs, probs, precision, tol=tol)
+    rel = 1e-10 if precision == hb.HUBBARD_FP64 else 1e-6
+    for g, h, p in zip(got, hs, probs):
+        ref = _oracle_run(p)
+        assert g["E0"] == pytest.approx(ref["E0"], rel=rel), p.name
+        assert g["stop"] in ("converged", "breakdown", "exhausted"), p.name
+        assert 0 <= g["err_est"] < 1e-3, p.name
+        solo = _lanczos_gpu(h, p, precision, tol, 300)
+        assert g["E0"] == pytest.approx(solo["E0"], rel=rel), p.name
+        if precision == hb.HUBBARD_FP64:
+            assert np.allclose(g["a"][:10], solo["a"][:10], rtol=1e-12, atol=1e-13)
+
+
+def test_batch_result_independent_of_mix():
+    """An instance gives bitwise the same a_j, b_{j+1}, E0 alone and inside a
+    batch of 64 (per-instance work items and fixed-order reductions)."""
+    probs = workload.batch64(64)
+    hs = [_build(p) for p in probs]
+    mix = _batch(hs, probs, hb.HUBBARD_MIXED)
+    for k in (0, 17, 63):
+        alone = _batch([hs[k]], [probs[k]], hb.HUBBARD_MIXED)[0]
+        assert alone["n_iter"] == mix[k]["n_iter"]
+        assert np.array_equal(alone["a"], mix[k]["a"]) and np.array_equal(alone["b"], mix[k]["b"])
+        assert alone["E0"] == mix[k]["E0"]
+
+
+def test_batch_with_psi_requests_and_large_rows():
+    """Solves that ask for psi, or whose rows exceed the batched kernels' LDS,
+    run on the single-instance path inside the same call."""
+    probs = workload.batch64(3) + [workload.problem("wide", 18, workload.ring(18), 1, 9, 1.0, 3.0, seed=7)]
+    hs = [_build(p) for p in probs]
+    psis = [None, torch.empty(probs[1].dim, dtype=torch.float64, device=DEV), None, None]
+    got = _batch(hs, probs, hb.HUBBARD_FP64, tol=1e-12, psis=psis)
+    for g, p in zip(got, probs):
+        assert g["E0"] == pytest.approx(_oracle_run(p)["E0"], rel=1e-10), p.name
+    assert got[1]["residual"] >= 0 and got[0]["residual"] == -1
