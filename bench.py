@@ -89,6 +89,88 @@ def time_lanczos(hb, torch, h, precision, steps, warmup, seed):
     return time.perf_counter() - t0, r
 
 
+def bench_batch(hb, torch, count):
+    """64 independent small solves (rings of 10-12 sites, mixed precision) in one
+    batched call, against the same solves run one by one in plain FP64; both are
+    checked against tol 1e-10 on E0."""
+    import workload
+    probs = workload.batch64(count)
+    hs = [hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U) for p in probs]
+    seeds = [p.seed for p in probs]
+    hb.hubbard_lanczos_batch(hs[:4], tol=1e-10, max_iter=300, precision=hb.HUBBARD_MIXED, seeds=seeds[:4])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mixed = hb.hubbard_lanczos_batch(hs, tol=1e-10, max_iter=300, precision=hb.HUBBARD_MIXED, seeds=seeds)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plain = [hb.hubbard_lanczos_ex(h, tol=1e-10, max_iter=300, precision=hb.HUBBARD_FP64, seed=p.seed,
+                                   history=False) for h, p in zip(hs, probs)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    worst = max(abs(m["E0"] - q["E0"]) / abs(q["E0"]) for m, q in zip(mixed, plain))
+    iters = sum(m["n_iter"] for m in mixed)
+    return {"solves": count, "batched_mixed_s": round(t_batch, 4), "plain_fp64_one_by_one_s": round(t_plain, 4),
+            "speedup": round(t_plain / t_batch, 2), "solves_per_s": round(count / t_batch, 1),
+            "iters_per_s": round(iters / t_batch, 1),
+            "max_rel_E0_diff_mixed_vs_fp64": float("%.3g" % worst),
+            "max_err_est": float("%.3g" % max(m["err_est"] for m in mixed))}
+
+
+def bench_serving(hb, torch, count, seed_rate=None):
+    """Continuous-batching server on the serving stream (3x4 / 4x4 tori with 4-8
+    electrons per spin, rings of 12-16 at half filling, U in [0, 12], mixed
+    precision).  A closed-loop run (all submitted at once) gives the capacity;
+    then `count` requests arrive as a Poisson stream at 0.7 x capacity."""
+    import numpy as np
+    import workload
+    budget = int(torch.cuda.get_device_properties(0).total_memory * 0.6)
+
+    def run(trace, paced):
+        srv = hb.hubbard_server_create(budget, 64)
+        t0 = time.perf_counter()
+        ids = {}
+        for t_arr, p in trace:
+            if paced:
+                wait = t_arr - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+            ids[hb.hubbard_server_submit(srv, p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U, tol=1e-8, max_iter=300,
+                                         precision=hb.HUBBARD_MIXED, seed=p.seed)] = p
+        done = {}
+        while len(done) < len(ids):
+            for c in hb.hubbard_server_poll(srv, cap=256, timeout_us=100000):
+                done[c["id"]] = c
+            if time.perf_counter() - t0 > 600:
+                raise RuntimeError("serving run did not finish")
+        wall = time.perf_counter() - t0
+        st = hb.hubbard_server_stats(srv)
+        hb.hubbard_server_destroy(srv)
+        return wall, list(done.values()), st
+
+    trace = workload.serving_trace(count, rate_per_s=1e9)
+    log("serving: closed loop,", count, "requests")
+    wall, res, _ = run(trace, paced=False)
+    capacity = len(res) / wall
+    rate = 0.7 * capacity
+    trace = workload.serving_trace(count, rate_per_s=rate)
+    log("serving: Poisson arrivals at %.2f/s" % rate)
+    wall, res, st = run(trace, paced=True)
+    ok = [c for c in res if c["status"] in (0, 1)]
+    lat = np.array([c["t_done"] - c["t_submit"] for c in ok])
+    svc = np.array([c["t_done"] - c["t_start"] for c in ok])
+    dims = sum(c["n_iter"] for c in ok)
+    return {"requests": count, "completed": len(ok), "failed": len(res) - len(ok),
+            "closed_loop_capacity_solves_per_s": round(capacity, 2), "arrival_rate_per_s": round(rate, 2),
+            "throughput_solves_per_s": round(len(ok) / wall, 2),
+            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+            "service_p50_s": round(float(np.percentile(svc, 50)), 4),
+            "service_p99_s": round(float(np.percentile(svc, 99)), 4),
+            "lanczos_steps": int(dims), "peak_reserved_gb": round(st["peak_reserved"] / 1e9, 2),
+            "budget_gb": round(st["budget"] / 1e9, 1), "max_active_batch": st["max_active_batch"]}
+
+
 def cpu_baseline(p):
     """The oracle, as it stands, on one host core: one Lanczos iteration of the
     same sector (model build and start vector outside the timing)."""
@@ -121,14 +203,16 @@ def stored_traffic(dim):
 # ------------------------------------------------------------------ summaries
 
 def _kernel_family(name):
-    for fam in ("hv_rows_kernel", "hv_slabs_kernel", "hv_kernel", "axpy_norm_kernel", "reduce_kernel",
-                "start_fill_kernel", "psi_acc_kernel", "copyBuffer", "elementwise"):
+    for fam in ("hv_rows_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel", "axpy_norm_kernel",
+                "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
+                "psi_acc_kernel", "batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "copyBuffer",
+                "elementwise"):
         if fam in name:
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""
-            if fam in ("hv_rows_kernel", "hv_slabs_kernel"):
+            if fam in ("hv_rows_kernel", "hv_blocks_kernel", "hv_slabs_kernel"):
                 inner = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "")
-                mode = {"0": "store", "1": "lanczos", "2": "residual"}.get(inner.split(",")[-1], "")
+                mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused"}.get(inner.split(",")[-1], "")
             return " ".join(x for x in (fam, prec, mode) if x)
     return name[:60]
 
@@ -192,7 +276,7 @@ def summarize_pmc(dfetch, dwrite):
         nw, bw = write.get(k, (0, 0.0))
         print("# %-34s %6d %14.4f %14.4f" % (k, max(nf, nw), bf * sf / 1e9, bw * sw / 1e9))
     hv = 0.0
-    for k in ("hv_rows_kernel f64 store", "hv_slabs_kernel f64 store"):
+    for k in ("hv_rows_kernel f64 store", "hv_blocks_kernel f64 store", "hv_slabs_kernel f64 store"):
         hv += fetch.get(k, (0, 0.0))[1] * sf + write.get(k, (0, 0.0))[1] * sw
     import workload
     print("source_sha", source_hash())
@@ -211,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--batch", type=int, default=64, help="solves in the batch leg (0 skips it)")
+    ap.add_argument("--serve", type=int, default=200, help="requests in the serving leg (0 skips it)")
     ap.add_argument("--summarize-trace")
     ap.add_argument("--summarize-pmc", nargs=2)
     args = ap.parse_args()
@@ -280,9 +366,16 @@ def main():
                      "traffic": None if traffic is None else round(traffic),
                      "traffic_unit": "HBM bytes per H.v (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_over_algorithmic": None if traffic is None else round(traffic / (2 * p.dim * 8), 3),
-                     "kernel": "FP64 H.v = hv_rows_kernel + hv_slabs_kernel (store mode, padded rows)",
+                     "kernel": "FP64 H.v = hv_rows_kernel + hv_blocks_kernel (store mode, padded rows)",
                      "algorithmic_bytes_per_launch": 2 * p.dim * 8},
     }
+    if args.batch:
+        log("batch leg:", args.batch, "solves")
+        out["batch"] = bench_batch(hb, torch, args.batch)
+    if args.serve:
+        out["serving"] = bench_serving(hb, torch, args.serve)
+        out["latency_p50_s"] = out["serving"]["latency_p50_s"]
+        out["latency_p99_s"] = out["serving"]["latency_p99_s"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one core)")
         cb = cpu_baseline(p)
