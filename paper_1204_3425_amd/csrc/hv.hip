@@ -101,19 +101,41 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
     const int64_t ddn = p.dim_dn;
     const int64_t slot = ddn + 1;  // staged row length including the zero slot
     const T mt = (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta, c_s = (T)cshift;
+    // staging: each thread loads CH elements of each of the RPB rows before it
+    // writes any of them to LDS, so a row costs one or two memory round trips
+    constexpr int CH = (MODE == HV_FUSED ? 8 : 16) / RPB;
+    const int ddn32 = (int)ddn, nth = (int)blockDim.x;
 
     for (int64_t r0 = (int64_t)blockIdx.x * RPB; r0 < p.dim_up; r0 += (int64_t)gridDim.x * RPB) {
         const int nr = (int)min((int64_t)RPB, p.dim_up - r0);
-        for (int64_t i = threadIdx.x; i < ddn * nr; i += blockDim.x) {
-            const int64_t q = i / ddn, d = i - q * ddn;
-            if (MODE == HV_FUSED) {
-                // the q - a_j f_j update of the previous step, formed here and kept
-                T *xp = const_cast<T *>(x) + (r0 + q) * ldx + d;
-                const T v = *xp - c_s * y[(r0 + q) * ldy + d];
-                *xp = v;
-                xs[q * slot + d] = v;
-            } else {
-                xs[q * slot + d] = x[(r0 + q) * ldx + d];
+        for (int d0 = 0; d0 < ddn32; d0 += CH * nth) {
+            T v[RPB][CH], w[RPB][CH];
+#pragma unroll
+            for (int q = 0; q < RPB; q++) {
+#pragma unroll
+                for (int u = 0; u < CH; u++) {
+                    const int d = d0 + u * nth + (int)threadIdx.x;
+                    const bool ok = q < nr && d < ddn32;
+                    v[q][u] = ok ? x[(r0 + q) * ldx + d] : (T)0;
+                    if (MODE == HV_FUSED)
+                        w[q][u] = ok ? y[(r0 + q) * ldy + d] : (T)0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RPB; q++) {
+#pragma unroll
+                for (int u = 0; u < CH; u++) {
+                    const int d = d0 + u * nth + (int)threadIdx.x;
+                    if (q < nr && d < ddn32) {
+                        T val = v[q][u];
+                        if (MODE == HV_FUSED) {
+                            // the q - a_j f_j update of the previous step, formed here and kept
+                            val = val - c_s * w[q][u];
+                            const_cast<T *>(x)[(r0 + q) * ldx + d] = val;
+                        }
+                        xs[q * slot + d] = val;
+                    }
+                }
             }
         }
         if (threadIdx.x < RPB)
@@ -332,9 +354,21 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
         const int64_t b0 = p.bstart[blk];
         const int bs = p.bstart[blk + 1] - (int)b0;
         const int64_t d0 = (int64_t)s * SL;
-        for (int i = threadIdx.x; i < bs * 8; i += blockDim.x) {
-            const int rr = i >> 3, q = i & 7;
-            xs[i] = load_row(x + (b0 + rr) * ldx, d0 + q * EPL);
+        // the block's slab segment: eight loads in flight per thread before
+        // the first LDS write
+        for (int i0 = 0; i0 < bs * 8; i0 += 8 * (int)blockDim.x) {
+            vec v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                v[u] = i < bs * 8 ? load_row(x + (b0 + (i >> 3)) * ldx, d0 + (i & 7) * EPL) : (vec)(T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i < bs * 8)
+                    xs[i] = v[u];
+            }
         }
         __syncthreads();
         const int sub = lane >> 3, q = lane & 7;
