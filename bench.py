@@ -48,16 +48,22 @@ def log(*a):
 
 
 def source_hash():
+    """Hash of the H.v kernel sources with comments and blank lines removed, so
+    that stored counter results stay valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     for f in HV_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 
-def time_hv(hb, torch, h, precision, launches, warmup):
-    """Mean time of one H.v (row pass + slab pass) on padded rows, from HIP
-    events recorded on the stream the kernels run on."""
+def time_hv(hb, torch, h, precision, launches, warmup, median=False):
+    """Mean (or median) time of one H.v (row pass + slab pass) on padded rows,
+    from HIP events recorded on the stream the kernels run on."""
     hb.hubbard_set_precision(h, precision)
     ld = hb.hubbard_info(h)["ld_pref"]
     dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
@@ -70,6 +76,15 @@ def time_hv(hb, torch, h, precision, launches, warmup):
     for _ in range(warmup):
         hb.hubbard_apply_ld(h, x, ld, y, ld)
     torch.cuda.synchronize()
+    if median:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
+        ev[0].record()
+        for i in range(launches):
+            hb.hubbard_apply_ld(h, x, ld, y, ld)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ts = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(launches))
+        return ts[launches // 2] * 1e-3
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(launches):
@@ -114,7 +129,8 @@ def bench_batch(hb, torch, count):
             "speedup": round(t_plain / t_batch, 2), "solves_per_s": round(count / t_batch, 1),
             "iters_per_s": round(iters / t_batch, 1),
             "max_rel_E0_diff_mixed_vs_fp64": float("%.3g" % worst),
-            "max_err_est": float("%.3g" % max(m["err_est"] for m in mixed))}
+            "max_err_est": float("%.3g" % max(m["err_est"] for m in mixed)),
+            "mixed_E0": [m["E0"] for m in mixed], "plain_E0": [q["E0"] for q in plain]}, probs
 
 
 def bench_serving(hb, torch, count, seed_rate=None):
@@ -171,6 +187,99 @@ def bench_serving(hb, torch, count, seed_rate=None):
             "budget_gb": round(st["budget"] / 1e9, 1), "max_active_batch": st["max_active_batch"]}
 
 
+def golden(name):
+    """A stored oracle run (written by tests/golden/make_oracle_golden.py)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def bench_ring14(hb, torch, launches):
+    """14-site ring, 7 up + 7 down, U=4 (dim 11,778,624): median H.v time over
+    `launches` launches per precision and the tol-stopped Lanczos solve against
+    the stored oracle run.  x is 94 MB in FP64, so it stays in the Infinity
+    Cache: the GB/s here is cache bandwidth, not HBM."""
+    import workload
+    p = workload.ring14()
+    h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    hb.hubbard_set_stream(h, torch.cuda.current_stream().cuda_stream)
+    g = golden("oracle_ring14.json")
+    out = {"dim": p.dim, "note": "x fits the 256 MB Infinity Cache: GB/s is cache bandwidth, not HBM"}
+    for name, prec, es in (("fp64", hb.HUBBARD_FP64, 8), ("mixed", hb.HUBBARD_MIXED, 4)):
+        t_med = time_hv(hb, torch, h, prec, launches, 5, median=True)
+        t0 = time.perf_counter()
+        r = hb.hubbard_lanczos_ex(h, tol=1e-12 if prec == hb.HUBBARD_FP64 else 1e-10, max_iter=400,
+                                  precision=prec, seed=p.seed, history=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        o = {"hv_median_us": round(t_med * 1e6, 1), "hv_gbs": round(2.0 * p.dim * es / t_med / 1e9, 1),
+             "solve_s": round(dt, 4), "iters": r["n_iter"], "iters_per_s": round(r["n_iter"] / dt, 1),
+             "E0": r["E0"]}
+        if g is not None:
+            o["E0_rel_err_vs_oracle"] = float("%.3g" % (abs(r["E0"] - g["E0"]) / abs(g["E0"])))
+        out[name] = o
+    return out
+
+
+def bench_ring8(hb, torch):
+    """8-site ring, 4 up + 4 down, U=4 (dim 4,900): a latency-bound solve to
+    tol 1e-12 (compared with the oracle in the CPU-baseline leg)."""
+    import workload
+    p = workload.ring8()
+    h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    hb.hubbard_set_stream(h, torch.cuda.current_stream().cuda_stream)
+    hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=p.seed, history=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=p.seed, history=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"dim": p.dim, "iters_to_converge": r["n_iter"], "solve_s": round(dt, 5), "E0": r["E0"]}
+
+
+def oracle_ring8(gpu):
+    """The oracle's solve of the 8-site ring: its time and the GPU's E0 error."""
+    import oracle
+    import workload
+    p = workload.ring8()
+    m = oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    f1 = oracle.start_vector(p.seed, m.dim)
+    t0 = time.perf_counter()
+    r = m.lanczos(f1, tol=1e-12, max_iter=300)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 2), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "one tol-1e-12 solve of the 8-site ring: %.4f s, %d iterations" % (dt, r["n_iter"]),
+            "gpu_E0_rel_err_vs_oracle": float("%.3g" % (abs(gpu["E0"] - r["E0"]) / abs(r["E0"])))}
+
+
+def _oracle_solve(args):
+    import oracle
+    sites, edges, n_up, n_dn, t, U, seed, tol = args
+    m = oracle.Model(sites, edges, n_up, n_dn, t, U)
+    return m.lanczos(oracle.start_vector(seed, m.dim), tol=tol, max_iter=300)["E0"]
+
+
+def oracle_batch_check(batch_probs, batch_res):
+    """The oracle on every instance of the batch leg, as independent processes
+    over the host cores: per-instance E0 errors of the batched mixed solves and
+    of the plain FP64 solves, and the oracle's own throughput."""
+    import multiprocessing as mp
+    ncores = min(16, os.cpu_count() or 1)
+    jobs = [(p.sites, [tuple(e) for e in p.edges], p.n_up, p.n_dn, p.t, p.U, p.seed, 1e-12) for p in batch_probs]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(ncores) as pool:
+        ref = pool.map(_oracle_solve, jobs, chunksize=1)
+    dt = time.perf_counter() - t0
+    err_mixed = max(abs(m - r) / abs(r) for m, r in zip(batch_res["mixed_E0"], ref))
+    err_plain = max(abs(q - r) / abs(r) for q, r in zip(batch_res["plain_E0"], ref))
+    return {"value": round(len(jobs) / dt, 3), "unit": "solves/s", "cores": ncores, "kind": "oracle",
+            "sample": "the %d batch-leg solves to tol 1e-12, one oracle process per solve: %.1f s" % (len(jobs), dt),
+            "max_rel_E0_err_batched_mixed": float("%.3g" % err_mixed),
+            "max_rel_E0_err_plain_fp64": float("%.3g" % err_plain)}
+
+
 def cpu_baseline(p):
     """The oracle, as it stands, on one host core: one Lanczos iteration of the
     same sector (model build and start vector outside the timing)."""
@@ -203,16 +312,19 @@ def stored_traffic(dim):
 # ------------------------------------------------------------------ summaries
 
 def _kernel_family(name):
-    for fam in ("hv_rows_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel", "axpy_norm_kernel",
+    for fam in ("hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel",
+                "axpy_norm_kernel",
                 "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
                 "psi_acc_kernel", "batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "copyBuffer",
                 "elementwise"):
         if fam in name:
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""
-            if fam in ("hv_rows_kernel", "hv_blocks_kernel", "hv_slabs_kernel"):
-                inner = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "")
-                mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused"}.get(inner.split(",")[-1], "")
+            if fam in ("hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel"):
+                targs = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "").split(",")
+                k = 2 if fam == "hv_rows_kernel" else 1
+                mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused"}.get(
+                    targs[k] if len(targs) > k else "", "")
             return " ".join(x for x in (fam, prec, mode) if x)
     return name[:60]
 
@@ -276,7 +388,8 @@ def summarize_pmc(dfetch, dwrite):
         nw, bw = write.get(k, (0, 0.0))
         print("# %-34s %6d %14.4f %14.4f" % (k, max(nf, nw), bf * sf / 1e9, bw * sw / 1e9))
     hv = 0.0
-    for k in ("hv_rows_kernel f64 store", "hv_blocks_kernel f64 store", "hv_slabs_kernel f64 store"):
+    for k in ("hv_rows_kernel f64 store", "hv_lines_kernel f64 store", "hv_blocks_kernel f64 store",
+              "hv_slabs_kernel f64 store"):
         hv += fetch.get(k, (0, 0.0))[1] * sf + write.get(k, (0, 0.0))[1] * sw
     import workload
     print("source_sha", source_hash())
@@ -297,6 +410,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="solves in the batch leg (0 skips it)")
     ap.add_argument("--serve", type=int, default=200, help="requests in the serving leg (0 skips it)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 14-site and 8-site ring legs")
     ap.add_argument("--summarize-trace")
     ap.add_argument("--summarize-pmc", nargs=2)
     args = ap.parse_args()
@@ -340,6 +454,11 @@ def main():
 
     f64 = res["fp64"]
     traffic = stored_traffic(p.dim)
+    g = golden("oracle_square4x4.json")
+    e0_err = None
+    if g is not None and g["n_iter"] == args.steps:
+        # the stored oracle run is the same recurrence from the same seed, 200 steps
+        e0_err = {k: float("%.3g" % (abs(v["E0"] - g["E0"]) / abs(g["E0"]))) for k, v in res.items()}
     out = {
         "metric": METRIC,
         "value": round(f64["hv_gbs"], 1),
@@ -361,17 +480,24 @@ def main():
         "hv_us": {k: round(v["hv_s"] * 1e6, 1) for k, v in res.items()},
         "hv_gbs": {k: round(v["hv_gbs"], 1) for k, v in res.items()},
         "E0": {k: v["E0"] for k, v in res.items()},
+        "E0_rel_err_vs_oracle": e0_err,
         "roofline": {"bound": "hbm", "achieved": round(f64["hv_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(f64["hv_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "traffic_unit": "HBM bytes per H.v (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_over_algorithmic": None if traffic is None else round(traffic / (2 * p.dim * 8), 3),
-                     "kernel": "FP64 H.v = hv_rows_kernel + hv_blocks_kernel (store mode, padded rows)",
+                     "kernel": "FP64 H.v = hv_rows_kernel + hv_lines_kernel (store mode, padded rows)",
                      "algorithmic_bytes_per_launch": 2 * p.dim * 8},
     }
+    if not args.no_small:
+        log("ring14 leg")
+        out["ring14"] = bench_ring14(hb, torch, 51)
+        log("ring8 leg")
+        out["ring8"] = bench_ring8(hb, torch)
+    batch_probs = None
     if args.batch:
         log("batch leg:", args.batch, "solves")
-        out["batch"] = bench_batch(hb, torch, args.batch)
+        out["batch"], batch_probs = bench_batch(hb, torch, args.batch)
     if args.serve:
         out["serving"] = bench_serving(hb, torch, args.serve)
         out["latency_p50_s"] = out["serving"]["latency_p50_s"]
@@ -380,7 +506,16 @@ def main():
         log("cpu baseline (oracle, one core)")
         cb = cpu_baseline(p)
         cb["gpu_fp64_over_cpu"] = round(out["lanczos_iters_per_s"]["fp64"] / cb["value"], 1)
+        if "ring8" in out:
+            cb["ring8"] = oracle_ring8(out["ring8"])
+        if batch_probs is not None:
+            log("oracle on the batch-leg solves")
+            ob = oracle_batch_check(batch_probs, out["batch"])
+            ob["gpu_batched_over_cpu"] = round(out["batch"]["solves_per_s"] / ob["value"], 1)
+            cb["batch"] = ob
         out["cpu_baseline"] = cb
+    if "batch" in out:
+        del out["batch"]["mixed_E0"], out["batch"]["plain_E0"]
     print(json.dumps(out), flush=True)
 
 

@@ -97,7 +97,8 @@ static void free_device(hubbard *h)
 {
     DeviceTables &d = h->dev;
     void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
-                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.up_blk, d.up_nint, d.up_next, d.up_bstart};
+                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.up_blk, d.up_nint, d.up_next,
+                    d.up_bstart, d.up_line, d.up_cnt};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -174,6 +175,20 @@ static void upload_blocked_up(hubbard *h, size_t &total)
         nint[(size_t)r] = (uint16_t)ni;
         next[(size_t)r] = (uint16_t)ne;
     }
+    if (up.width <= 32) {
+        std::vector<uint32_t> line((size_t)du * 32, 0u), cnt((size_t)du);
+        for (int64_t r = 0; r < du; r++) {
+            const size_t o = (size_t)r * (size_t)w;
+            const int ni = nint[(size_t)r], ne = next[(size_t)r];
+            for (int k = 0; k < ni; k++)
+                line[(size_t)r * 32 + (size_t)k] = ent[o + (size_t)k];
+            for (int k = 0; k < ne; k++)
+                line[(size_t)r * 32 + 31 - (size_t)k] = ent[o + (size_t)(ni + k)];
+            cnt[(size_t)r] = (uint32_t)ni | ((uint32_t)ne << 16);
+        }
+        d.up_line = upload<uint32_t>(line.data(), line.size() * 4, total);
+        d.up_cnt = upload<uint32_t>(cnt.data(), cnt.size() * 4, total);
+    }
     d.up_blk = upload<uint32_t>(ent.data(), ent.size() * 4, total);
     d.up_nint = upload<uint16_t>(nint.data(), nint.size() * 2, total);
     d.up_next = upload<uint16_t>(next.data(), next.size() * 2, total);
@@ -229,6 +244,24 @@ static void upload_tables(hubbard *h)
         (es == 8 ? d.dn_groups64 : d.dn_groups32) = dev;
     }
     d.dn_nq = upload<uint8_t>(nq.data(), nq.size(), total);
+    if (ddn < 32768) {
+        // entry k of column d at ((k/8) * dim_dn + d) * 8 + k%8; padding = the zero slot's index
+        const int ng8 = (h->dn.width + 7) / 8;
+        std::vector<uint16_t> g((size_t)std::max(ng8, 1) * (size_t)ddn * 8, (uint16_t)ddn);
+        std::vector<uint8_t> nq8((size_t)((ddn + 63) / 64), 0);
+        for (int64_t r = 0; r < ddn; r++) {
+            const int nnz = h->dn.row_nnz[(size_t)r];
+            for (int k = 0; k < nnz; k++) {
+                size_t src = (size_t)k * (size_t)ddn + (size_t)r;
+                g[((size_t)(k / 8) * (size_t)ddn + (size_t)r) * 8 + (size_t)(k % 8)] =
+                    (uint16_t)((uint32_t)h->dn.col[src] | (h->dn.sgn[src] < 0 ? 0x8000u : 0u));
+            }
+            uint8_t &slot = nq8[(size_t)(r / 64)];
+            slot = (uint8_t)std::max<int>(slot, (nnz + 7) / 8);
+        }
+        d.dn_groups16 = upload<uint16_t>(g.data(), g.size() * 2, total);
+        d.dn_nq8 = upload<uint8_t>(nq8.data(), nq8.size(), total);
+    }
     upload_blocked_up(h, total);
     d.bytes = total;
 }
@@ -246,12 +279,16 @@ static HvArgs hv_args(const hubbard *h)
     a.dn_groups32 = reinterpret_cast<const uint4 *>(h->dev.dn_groups32);
     a.dn_nq = h->dev.dn_nq;
     a.dn_ngroups = h->dev.dn_ngroups;
+    a.dn_groups16 = reinterpret_cast<const uint4 *>(h->dev.dn_groups16);
+    a.dn_nq8 = h->dev.dn_nq8;
     a.up_blk = h->dev.up_blk;
     a.up_nint = h->dev.up_nint;
     a.up_next = h->dev.up_next;
     a.up_bstart = h->dev.up_bstart;
     a.up_nblocks = h->dev.up_nblocks;
     a.up_max_block = h->dev.up_max_block;
+    a.up_line = h->dev.up_line;
+    a.up_cnt = h->dev.up_cnt;
     a.dim_up = h->up.dim;
     a.dim_dn = h->dn.dim;
     a.w_up = h->up.width;

@@ -7,33 +7,37 @@
 // its own:
 //
 // Row pass (I (x) H_dn and the interaction).  A workgroup stages whole rows of
-// X in LDS (RPB rows at once, each followed by a zero slot) and every lane
-// produces the outputs of its columns d by gathering X[r, e_k(d)] from LDS.
-// The down table is stored as groups of four 32-bit entries per column d
-// (byte offset of the source element in the staged row, sign in bit 31), and
-// all groups of a column are loaded before the first gather so the table
-// latency is paid once.  Padding entries point at the zero slot, so no lane
-// tests how many entries it owns; the sign of the hop is applied by flipping
-// the sign bit of the gathered value.  The group count is the maximum over the
-// 64 columns of a wave.
+// X in LDS (RPB rows at once, each followed by a zero slot; every thread loads
+// its chunk before writing any of it) and every lane produces the outputs of
+// its columns d by gathering X[r, e_k(d)] from LDS.  The down table is stored
+// in groups per column d: eight 16-bit entries (element index, sign in bit 15)
+// when a row has fewer than 32768 elements, else four 32-bit entries (byte
+// offset, sign in bit 31).  All groups of a column are loaded before the first
+// gather; padding entries point at the zero slot, so no lane tests how many
+// entries it owns; the sign of a hop flips the sign bit of the gathered value.
+// The group count is the maximum over the 64 columns of a wave.
 //
-// Slab pass (H_up (x) I).  Output row r is a signed sum of whole rows
-// X[c_k(r), :].  Each XCD of the MI355X (workgroup i runs on XCD i mod 8)
-// sweeps its own 64-column slabs, so the slab of X that the row combinations
-// re-read stays in that XCD's 4 MB L2 while every CU of the XCD works on it.
-// A workgroup owns a fixed block of rows and keeps their up-hopping entries
-// in LDS for the whole sweep; one wave handles one row of a slab, so a row's
-// entries are wave-uniform and the row loop has no divergence.  The running
-// output is read and written with non-temporal accesses so it does not evict
-// the slab.  Rows of internal vectors are padded to a multiple of 64 elements
-// so a slab segment never straddles cache lines shared with the next slab.
+// Up-spin pass (H_up (x) I).  Output row r is a signed sum of whole rows
+// X[c_k(r), :].  Rows are grouped in blocks of equal occupation of the top
+// sites (a contiguous range in the ascending order).  Workgroup b handles one
+// 128-byte slab of one block, numbered slab-major per XCD (workgroup i runs on
+// XCD i mod 8), so the rows that other blocks' hops re-read are still in that
+// XCD's 4 MB L2.  The block's slab segment is staged in LDS and serves the
+// hops that stay inside the block; the others read global memory.  Eight
+// lanes cover one row segment with 16-byte accesses, so a wave updates eight
+// rows.  hv_lines_kernel takes a row's entries as one 128-byte line (rows of at
+// most 32 hops); hv_blocks_kernel handles longer rows.  hv_slabs_kernel serves
+// caller buffers whose row stride is not a multiple of 128 bytes.  The running
+// output is read and written with non-temporal accesses.
 //
 // Epilogues (both passes together):
 //   HV_STORE    y = H x
 //   HV_LANCZOS  y = alpha H x + beta y, partial sums of y.x    (alpha, beta on the device)
+//   HV_FUSED    x <- x - c y first (row pass), then as HV_LANCZOS, partial sums
+//               of y.x, y.y and x.x
 //   HV_RESIDUAL z = H x - alpha x (not stored), partial sums of z.z and x.Hx
-// Partial sums are one FP64 value per slab-pass workgroup, summed later in a
-// fixed order.
+// Partial sums are one FP64 value per up-spin-pass workgroup, summed later in
+// a fixed order.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -71,7 +75,7 @@ __device__ inline double flip_sign(double v, uint32_t sg)
 }
 
 struct RowArgs {
-    const uint4 *__restrict__ groups;  // [g][d] -> 4 entries
+    const uint4 *__restrict__ groups;  // [g][d] -> 4 entries of 32 bits, or 8 of 16 bits
     const uint8_t *__restrict__ nq;    // groups per 64 columns
     const uint32_t *__restrict__ states_up;
     const uint32_t *__restrict__ states_dn;
@@ -82,7 +86,7 @@ struct RowArgs {
 
 // Row pass.  MODE as in the file comment; for HV_RESIDUAL y is the scratch
 // vector z and alpha is the shift.
-template <typename T, int RPB, int MODE>
+template <typename T, int RPB, int MODE, bool G16>
 __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__restrict__ x, int64_t ldx,
                                                        T *__restrict__ y, int64_t ldy, double alpha, double beta,
                                                        const double *__restrict__ coef)
@@ -156,19 +160,30 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
 #pragma unroll
             for (int q = 0; q < RPB; q++)
                 h[q] = (T)0;
-            for (int g0 = 0; g0 < nq; g0 += 8) {
-                uint4 e4[8];
+            // 32 entries per batch of table loads: 8 groups of four 32-bit
+            // entries, or 4 groups of eight 16-bit entries
+            constexpr int GB = G16 ? 4 : 8;
+            for (int g0 = 0; g0 < nq; g0 += GB) {
+                uint4 e4[GB];
 #pragma unroll
-                for (int g = 0; g < 8; g++)
+                for (int g = 0; g < GB; g++)
                     if (g0 + g < nq)
                         e4[g] = gp[(int64_t)(g0 + g) * ddn];
 #pragma unroll
-                for (int g = 0; g < 8; g++) {
+                for (int g = 0; g < GB; g++) {
                     if (g0 + g < nq) {
                         const uint32_t ev[4] = {e4[g].x, e4[g].y, e4[g].z, e4[g].w};
 #pragma unroll
-                        for (int u = 0; u < 4; u++) {
-                            const uint32_t off = ev[u] & 0x7fffffffu, sg = ev[u] & 0x80000000u;
+                        for (int u = 0; u < (G16 ? 8 : 4); u++) {
+                            uint32_t off, sg;
+                            if (G16) {
+                                const uint32_t e = (ev[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
+                                off = (e & 0x7fffu) * (uint32_t)sizeof(T);
+                                sg = (e & 0x8000u) << 16;
+                            } else {
+                                off = ev[u] & 0x7fffffffu;
+                                sg = ev[u] & 0x80000000u;
+                            }
 #pragma unroll
                             for (int q = 0; q < RPB; q++) {
                                 const T v = *reinterpret_cast<const T *>(
@@ -485,6 +500,205 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
     }
 }
 
+struct LineArgs {
+    const uint4 *__restrict__ line;    // per row: 32 slots = 8 x uint4
+    const uint32_t *__restrict__ cnt;  // next << 16 | nint
+    const int32_t *__restrict__ bstart;
+    int64_t dim_up, dim_dn;
+    int nblocks, nslab;
+    double t;
+};
+
+// Blocked slab pass, line layout (rows of at most 32 hops).  Same workgroup
+// numbering and LDS staging as hv_blocks_kernel, plus a zero row after the
+// block that padding hops point at.  A row's entries are one 128-byte line
+// (internal hops from the front, external from the back), so each lane
+// group loads them with eight independent loads issued together with the
+// running output, and the hop counts come in one word.  Internal hops are
+// summed with the sign applied by flipping the sign bit; -t (and alpha)
+// multiply the sum once.  External rows are read four at a time.
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__restrict__ x, int64_t ldx,
+                                                        T *__restrict__ y, int64_t ldy, double alpha,
+                                                        const double *__restrict__ coef,
+                                                        double *__restrict__ partials)
+{
+    constexpr int EPL = 16 / (int)sizeof(T);  // elements per lane
+    constexpr int SL = 8 * EPL;               // slab width in elements
+    constexpr int XB = 4;                     // external rows in flight per lane
+    typedef __attribute__((ext_vector_type(EPL))) T vec;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    vec *xs = reinterpret_cast<vec *>(smem_raw);  // [row in block][8], row bs = 0
+    auto load_row = [&](const T *row, int64_t d) -> vec {
+        if (d + EPL <= p.dim_dn)
+            return *reinterpret_cast<const vec *>(row + d);
+        vec v;
+#pragma unroll
+        for (int e = 0; e < EPL; e++)
+            v[e] = d + e < p.dim_dn ? row[d + e] : (T)0;
+        return v;
+    };
+    __shared__ double red[16];
+    if (MODE == HV_LANCZOS)
+        alpha = coef[0];
+    else if (MODE == HV_FUSED)
+        alpha = coef[1];
+    // y += scale * sum_k (+-x_k): -t, times alpha in the Lanczos modes
+    const T scale = (MODE == HV_LANCZOS || MODE == HV_FUSED) ? (T)(alpha * -p.t) : (T)(-p.t);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwave = blockDim.x >> 6;
+    const int xcd = blockIdx.x & 7;
+    const int local = blockIdx.x >> 3;
+    const int s = (local / p.nblocks) * 8 + xcd;
+    const int blk = local % p.nblocks;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    if (s < p.nslab) {
+        const int64_t b0 = p.bstart[blk];
+        const int bs = p.bstart[blk + 1] - (int)b0;
+        const int64_t d0 = (int64_t)s * SL;
+        for (int i0 = 0; i0 < bs * 8; i0 += 8 * (int)blockDim.x) {
+            vec v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                v[u] = i < bs * 8 ? load_row(x + (b0 + (i >> 3)) * ldx, d0 + (i & 7) * EPL) : (vec)(T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i < bs * 8)
+                    xs[i] = v[u];
+            }
+        }
+        if (threadIdx.x < 8)
+            xs[bs * 8 + threadIdx.x] = (vec)(T)0;
+        __syncthreads();
+        const int sub = lane >> 3, q = lane & 7;
+        const int64_t d = d0 + q * EPL;
+        const bool dok = d < p.dim_dn, whole = d + EPL <= p.dim_dn;
+        for (int rb = wave * 8; rb < bs; rb += nwave * 8) {
+            const int rl = min(rb + sub, bs - 1);
+            const bool okr = rb + sub < bs;
+            const int64_t r = b0 + rl;
+            T *yp = y + r * ldy + d;
+            vec prev = (vec)(T)0;
+            if (okr && dok) {
+                if (whole) {
+                    prev = __builtin_nontemporal_load(reinterpret_cast<const vec *>(yp));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < EPL; e++)
+                        prev[e] = d + e < p.dim_dn ? yp[e] : (T)0;
+                }
+            }
+            uint4 E[8];
+#pragma unroll
+            for (int g = 0; g < 8; g++)
+                E[g] = p.line[r * 8 + g];
+            const uint32_t C = p.cnt[r];
+            const int ni = (int)(C & 0xffffu), ne = (int)(C >> 16);
+            int nim = ni, nem = ne;
+            for (int o = 8; o < 64; o <<= 1) {
+                nim = max(nim, __shfl_xor(nim, o, 64));
+                nem = max(nem, __shfl_xor(nem, o, 64));
+            }
+            nim = __builtin_amdgcn_readfirstlane(nim);
+            nem = __builtin_amdgcn_readfirstlane(nem);
+            uint32_t ev[32];
+#pragma unroll
+            for (int g = 0; g < 8; g++) {
+                ev[4 * g] = E[g].x;
+                ev[4 * g + 1] = E[g].y;
+                ev[4 * g + 2] = E[g].z;
+                ev[4 * g + 3] = E[g].w;
+            }
+            vec acc = (vec)(T)0;
+#pragma unroll
+            for (int k0 = 0; k0 < 32; k0 += 8) {
+                if (k0 < nim) {
+                    vec v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int li = k0 + u < ni ? (int)(ev[k0 + u] & 0x7fffffffu) : bs;
+                        v[u] = xs[li * 8 + q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const uint32_t sg = ev[k0 + u] & 0x80000000u;
+#pragma unroll
+                        for (int c = 0; c < EPL; c++)
+                            acc[c] += flip_sign(v[u][c], sg);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k0 = 0; k0 < 32; k0 += XB) {
+                if (k0 < nem) {
+                    vec v[XB];
+#pragma unroll
+                    for (int u = 0; u < XB; u++) {
+                        const bool live = k0 + u < ne;
+                        const int64_t row = live ? (int64_t)(ev[31 - (k0 + u)] & 0x7fffffffu) : r;
+                        v[u] = load_row(x + row * ldx, d);
+                    }
+#pragma unroll
+                    for (int u = 0; u < XB; u++) {
+                        const bool live = k0 + u < ne;
+                        const uint32_t sg = ev[31 - (k0 + u)] & 0x80000000u;
+#pragma unroll
+                        for (int c = 0; c < EPL; c++)
+                            acc[c] += live ? flip_sign(v[u][c], sg) : (T)0;
+                    }
+                }
+            }
+            if (okr && dok) {
+                const vec xv = xs[rl * 8 + q];
+                const vec out = prev + scale * acc;  // in the residual mode prev = row pass of H x - alpha x
+#pragma unroll
+                for (int e = 0; e < EPL; e++) {
+                    if (d + e < p.dim_dn) {
+                        if (MODE == HV_LANCZOS) {
+                            acc0 += (double)out[e] * (double)xv[e];
+                        } else if (MODE == HV_FUSED) {
+                            acc0 += (double)out[e] * (double)xv[e];
+                            acc1 += (double)out[e] * (double)out[e];
+                            acc2 += (double)xv[e] * (double)xv[e];
+                        } else if (MODE == HV_RESIDUAL) {
+                            acc0 += (double)out[e] * (double)out[e];
+                            acc1 += (double)xv[e] * ((double)out[e] + alpha * (double)xv[e]);
+                        }
+                    }
+                }
+                if (MODE != HV_RESIDUAL) {
+                    if (whole) {
+                        __builtin_nontemporal_store(out, reinterpret_cast<vec *>(yp));
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < EPL; e++)
+                            if (d + e < p.dim_dn)
+                                yp[e] = out[e];
+                    }
+                }
+            }
+        }
+    }
+    if (MODE != HV_STORE) {
+        const double s0 = block_sum2(acc0, red);
+        if (threadIdx.x == 0)
+            partials[blockIdx.x] = s0;
+        if (MODE == HV_RESIDUAL || MODE == HV_FUSED) {
+            const double s1 = block_sum2(acc1, red);
+            if (threadIdx.x == 0)
+                partials[gridDim.x + blockIdx.x] = s1;
+        }
+        if (MODE == HV_FUSED) {
+            const double s2 = block_sum2(acc2, red);
+            if (threadIdx.x == 0)
+                partials[2 * gridDim.x + blockIdx.x] = s2;
+        }
+    }
+}
+
 template <typename T, int RPB>
 size_t row_lds(int64_t ddn)
 {
@@ -538,7 +752,8 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
         pl.blk_nslab = (int)((ddn + sl - 1) / sl);
         const int64_t per_xcd = (pl.blk_nslab + 7) / 8;
         pl.blk_grid = (int)(8 * per_xcd * a.up_nblocks);
-        pl.blk_lds = (size_t)a.up_max_block * 128;
+        // the line kernel stages a zero row after the block
+        pl.blk_lds = (size_t)(a.up_max_block + (a.up_line ? 1 : 0)) * 128;
         const int64_t thr = ((int64_t)a.up_max_block * 8 + 63) / 64 * 64;
         pl.blk_threads = (int)(thr < 1024 ? (thr < 256 ? 256 : thr) : 1024);
         pl.nparts = std::max(pl.nparts, pl.blk_grid);
@@ -547,8 +762,8 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
 }
 
 template <typename T, int RPB>
-static void launch_rows_rpb(const RowArgs &ra, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy,
-                            int mode, double alpha, const double *coef, hipStream_t s)
+static void launch_rows_rpb(const RowArgs &ra, bool g16, const HvPlan &pl, const T *x, int64_t ldx, T *y,
+                            int64_t ldy, int mode, double alpha, const double *coef, hipStream_t s)
 {
     const size_t lds = row_lds<T, RPB>(ra.dim_dn);
     auto go = [&](auto kern) {
@@ -557,14 +772,25 @@ static void launch_rows_rpb(const RowArgs &ra, const HvPlan &pl, const T *x, int
                            coef);
         HUB_HIP(hipGetLastError());
     };
-    if (mode == HV_STORE)
-        go(hv_rows_kernel<T, RPB, HV_STORE>);
-    else if (mode == HV_LANCZOS)
-        go(hv_rows_kernel<T, RPB, HV_LANCZOS>);
-    else if (mode == HV_FUSED)
-        go(hv_rows_kernel<T, RPB, HV_FUSED>);
-    else
-        go(hv_rows_kernel<T, RPB, HV_RESIDUAL>);
+    if (g16) {
+        if (mode == HV_STORE)
+            go(hv_rows_kernel<T, RPB, HV_STORE, true>);
+        else if (mode == HV_LANCZOS)
+            go(hv_rows_kernel<T, RPB, HV_LANCZOS, true>);
+        else if (mode == HV_FUSED)
+            go(hv_rows_kernel<T, RPB, HV_FUSED, true>);
+        else
+            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, true>);
+    } else {
+        if (mode == HV_STORE)
+            go(hv_rows_kernel<T, RPB, HV_STORE, false>);
+        else if (mode == HV_LANCZOS)
+            go(hv_rows_kernel<T, RPB, HV_LANCZOS, false>);
+        else if (mode == HV_FUSED)
+            go(hv_rows_kernel<T, RPB, HV_FUSED, false>);
+        else
+            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false>);
+    }
 }
 
 template <typename T>
@@ -580,8 +806,9 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
         return pl.nparts;
     }
     RowArgs ra;
-    ra.groups = sizeof(T) == 8 ? a.dn_groups64 : a.dn_groups32;
-    ra.nq = a.dn_nq;
+    const bool g16 = a.dn_groups16 != nullptr;
+    ra.groups = g16 ? a.dn_groups16 : (sizeof(T) == 8 ? a.dn_groups64 : a.dn_groups32);
+    ra.nq = g16 ? a.dn_nq8 : a.dn_nq;
     ra.states_up = a.states_up;
     ra.states_dn = a.states_dn;
     ra.dim_up = a.dim_up;
@@ -592,11 +819,11 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     T *yr = mode == HV_RESIDUAL ? scratch : y;
     const int64_t ldyr = mode == HV_RESIDUAL ? lds_ : ldy;
     if (pl.rows_rpb == 3)
-        launch_rows_rpb<T, 3>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+        launch_rows_rpb<T, 3>(ra, g16, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else if (pl.rows_rpb == 2)
-        launch_rows_rpb<T, 2>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+        launch_rows_rpb<T, 2>(ra, g16, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else
-        launch_rows_rpb<T, 1>(ra, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+        launch_rows_rpb<T, 1>(ra, g16, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
 
     const int64_t slw = 128 / (int64_t)sizeof(T);
     if (pl.blk_grid > 0 && ldx % slw == 0 && ldyr % slw == 0) {
@@ -619,6 +846,34 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                                alpha, coef, partials);
             HUB_HIP(hipGetLastError());
         };
+        if (a.up_line) {
+            LineArgs la;
+            la.line = reinterpret_cast<const uint4 *>(a.up_line);
+            la.cnt = a.up_cnt;
+            la.bstart = a.up_bstart;
+            la.dim_up = a.dim_up;
+            la.dim_dn = a.dim_dn;
+            la.nblocks = a.up_nblocks;
+            la.nslab = pl.blk_nslab;
+            la.t = a.t;
+            auto gol = [&](auto kern) {
+                if (pl.blk_lds > 64 * 1024)
+                    HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)pl.blk_lds));
+                hipLaunchKernelGGL(kern, dim3(pl.blk_grid), dim3(pl.blk_threads), pl.blk_lds, s, la, x, ldx, yr,
+                                   ldyr, alpha, coef, partials);
+                HUB_HIP(hipGetLastError());
+            };
+            if (mode == HV_STORE)
+                gol(hv_lines_kernel<T, HV_STORE>);
+            else if (mode == HV_LANCZOS)
+                gol(hv_lines_kernel<T, HV_LANCZOS>);
+            else if (mode == HV_FUSED)
+                gol(hv_lines_kernel<T, HV_FUSED>);
+            else
+                gol(hv_lines_kernel<T, HV_RESIDUAL>);
+            return pl.blk_grid;
+        }
         if (mode == HV_STORE)
             gob(hv_blocks_kernel<T, HV_STORE>);
         else if (mode == HV_LANCZOS)

@@ -48,6 +48,10 @@ struct DeviceTables {
     uint32_t *dn_groups64 = nullptr, *dn_groups32 = nullptr;
     uint8_t *dn_nq = nullptr;      // groups needed by the 64 columns of a wave
     int dn_ngroups = 0;
+    // the same table at half the size, for rows of at most 32767 elements:
+    // groups of eight 16-bit entries (element index | sign<<15)
+    uint16_t *dn_groups16 = nullptr;
+    uint8_t *dn_nq8 = nullptr;     // groups of eight needed by the 64 columns of a wave
     // up table for the blocked slab pass: rows are grouped in blocks of equal
     // occupation of the top sites; per row the hops that stay in the block come
     // first (block-local row | sign<<31), then the others (row | sign<<31)
@@ -55,6 +59,10 @@ struct DeviceTables {
     uint16_t *up_nint = nullptr, *up_next = nullptr;
     int32_t *up_bstart = nullptr;  // nblocks + 1 row offsets
     int up_nblocks = 0, up_max_block = 0;
+    // the same entries with one 32-slot line per row (rows of at most 32
+    // hops): internal hops from the front, external from the back; the two
+    // counts packed as next << 16 | nint
+    uint32_t *up_line = nullptr, *up_cnt = nullptr;
     size_t bytes = 0;
 };
 
@@ -95,10 +103,13 @@ struct HvArgs {
     const uint4 *dn_groups64, *dn_groups32;
     const uint8_t *dn_nq;
     int dn_ngroups;
+    const uint4 *dn_groups16;  // null when rows exceed 32767 elements
+    const uint8_t *dn_nq8;
     const uint32_t *up_blk;
     const uint16_t *up_nint, *up_next;
     const int32_t *up_bstart;
     int up_nblocks, up_max_block;
+    const uint32_t *up_line, *up_cnt;  // null when a row has more than 32 hops
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
     double t, U;

@@ -55,6 +55,22 @@ def _apply_gpu(h, x_np, precision):
     return y.double().cpu().numpy()
 
 
+def _apply_gpu_ld(h, x_np, precision):
+    """H x through hubbard_apply_ld on rows padded to ld_pref: the layout and
+    kernels the Lanczos driver and the benchmark use."""
+    hb.hubbard_set_precision(h, precision)
+    dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
+    ld = hb.hubbard_info(h)["ld_pref"]
+    xp = torch.zeros((h.dim_up, ld), dtype=dt, device=DEV)
+    xp[:, :h.dim_dn] = torch.from_numpy(x_np).to(DEV, dt).view(h.dim_up, h.dim_dn)
+    yp = torch.empty_like(xp)
+    hb.hubbard_apply_ld(h, xp, ld, yp, ld)
+    torch.cuda.synchronize()
+    out = yp[:, :h.dim_dn].double().cpu().numpy().reshape(-1)
+    del xp, yp
+    return out
+
+
 def _term_bound(p, info):
     return max(abs(p.U) * p.sites, abs(p.t)) * (1 + info["w_up"] + info["w_dn"])
 
@@ -96,11 +112,42 @@ def test_apply_matches_oracle(p, precision):
         assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref) + 1e-30
 
 
+PADDED_CASES = [
+    # more than 1024 up configurations: several row blocks, hops inside and across blocks
+    workload.problem("ring14", 14, workload.ring(14), 7, 7, 1.0, 4.0),
+    workload.problem("torus3x4_t07", 12, workload.torus(3, 4), 6, 5, 0.7, 3.0),
+    # every pair of 12 sites bonded: up rows of 36 hops (more than one 32-slot line)
+    workload.problem("complete12", 12, [(i, j) for i in range(12) for j in range(i + 1, 12)], 6, 2, 1.0, 2.0),
+    workload.problem("chain13_ragged", 13, workload.chain(13), 7, 3, 1.0, 5.0),
+]
+
+
+@pytest.mark.parametrize("p", PADDED_CASES, ids=[c.name for c in PADDED_CASES])
+@pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
+def test_apply_padded_rows_match_oracle(p, precision):
+    _say("apply padded", p.name, "dim", p.dim, "precision", precision)
+    h = _build(p)
+    m = _oracle(p)
+    x = workload.random_vector(p.dim, p.seed + 4)
+    if precision == hb.HUBBARD_MIXED:
+        x = x.astype(np.float32).astype(np.float64)
+    ref = m.apply(x)
+    got = _apply_gpu_ld(h, x, precision)
+    scale = max(1.0, np.abs(ref).max())
+    if precision == hb.HUBBARD_FP64:
+        assert np.abs(got - ref).max() <= 1e-13 * scale
+    else:
+        info = hb.hubbard_info(h)
+        bound = (1 + info["w_up"] + info["w_dn"]) * 2.0**-24 * _term_bound(p, info) * np.abs(x).max()
+        assert np.abs(got - ref).max() <= bound
+
+
 @pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
 def test_apply_4x4_sampled_rows(precision):
     """The 4x4 half-filled sector (dim 165,636,900) at full size, in the launch
-    configuration the benchmark uses: outputs checked on 3000 sampled rows
-    (including the first and last row and the last column)."""
+    configuration the benchmark uses (rows padded to ld_pref): outputs checked
+    on 3000 sampled rows (including the first and last row and the last
+    column), and the symmetry of H against the dense-row kernels."""
     p = workload.square4x4()
     _say("apply 4x4 sampled, precision", precision)
     h = _build(p)
@@ -108,7 +155,7 @@ def test_apply_4x4_sampled_rows(precision):
     x = workload.random_vector(p.dim, p.seed + 2)
     if precision == hb.HUBBARD_MIXED:
         x = x.astype(np.float32).astype(np.float64)
-    got = _apply_gpu(h, x, precision)
+    got = _apply_gpu_ld(h, x, precision)
     rng = np.random.default_rng(3)
     rows = np.concatenate([[0, p.dim - 1, p.dim_dn - 1, p.dim - p.dim_dn], rng.integers(0, p.dim, 3000)])
     ref = m.apply_rows(x, rows)
@@ -124,7 +171,7 @@ def test_apply_4x4_sampled_rows(precision):
     u = workload.random_vector(p.dim, p.seed + 3)
     if precision == hb.HUBBARD_MIXED:
         u = u.astype(np.float32).astype(np.float64)
-    Hu = _apply_gpu(h, u, precision)
+    Hu = _apply_gpu(h, u, precision)  # dense rows: the other up-spin kernel
     lhs, rhs = float(u @ got), float(Hu @ x)
     tol = 1e-11 if precision == hb.HUBBARD_FP64 else 1e-4
     assert abs(lhs - rhs) <= tol * (np.abs(u).sum() + np.abs(x).sum())
@@ -297,6 +344,19 @@ def test_lanczos_large_sector_matches_oracle():
             assert abs(got["psi"] @ ref["psi"]) > 1 - 1e-4
         assert got["residual"] == pytest.approx(
             np.linalg.norm(m.apply(got["psi"]) - got["E0"] * got["psi"]), rel=1e-6, abs=1e-12)
+
+
+def test_lanczos_wide_up_rows():
+    """Up rows of 36 hops (every pair of 12 sites bonded), 203,280 states: the
+    fused step on the blocked pass for rows longer than one 32-slot line."""
+    p = workload.problem("complete12_6u3d", 12, [(i, j) for i in range(12) for j in range(i + 1, 12)], 6, 3,
+                         1.0, 2.0)
+    h = _build(p)
+    assert hb.hubbard_info(h)["w_up"] > 32
+    ref = _oracle(p).lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-12, max_iter=300)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 300)
+    assert got["E0"] == pytest.approx(ref["E0"], rel=1e-10)
+    assert np.allclose(got["a"][:20], ref["a"][:20], rtol=1e-12, atol=1e-13)
 
 
 def test_lanczos_large_sector_breakdown():
