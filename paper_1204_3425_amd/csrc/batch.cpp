@@ -1,9 +1,12 @@
 // Host side of the batched Lanczos engine (kernels in batch.hip).
 //
 // Each call to step() advances every active instance by one step of Alg. 1
-// (Sec. 2.2) with four launches, then reads every instance's (a_j, b_{j+1})
-// from one mailbox copy and applies the energy test.  Converged instances
-// leave the batch; the work-item list is rebuilt only when the set changes.
+// (Sec. 2.2) with four launches.  The step's last kernel computes E_j and the
+// stop test on the device and writes every instance's {a_j, b_{j+1}, E_j,
+// code} to a mailbox; the host copies the mailboxes back asynchronously and
+// reads them kLookahead steps behind, so it never waits for the device inside
+// a run.  Stopped instances skip later steps; the descriptor table is rebuilt
+// when instances join or when every listed one has finished.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -53,23 +56,41 @@ struct Slot {
     hubbard *h = nullptr;
     hubbard_opts o{};
     hubbard_result *res = nullptr;
-    std::unique_ptr<Dev> work, scal, part;
+    std::unique_ptr<Dev> work, state, part, hist;
     int64_t rpi = 1;
     int nitems = 0;
-    int cur = 0;
+    int index = -1;  // position in the current descriptor table, -1 before the first rebuild
     std::vector<double> a, b, e;
-    double scale = 0.0;
     int stop = HUBBARD_STOP_MAXITER;
     bool done = false;
     std::chrono::steady_clock::time_point t0;
 };
 
+// Steps the device may run ahead of the host's reading of the mailboxes.
+constexpr int kLookahead = 4;
+
 template <typename T>
 class Engine : public BatchRunner {
   public:
-    explicit Engine(hipStream_t s) : s_(s) {}
+    explicit Engine(hipStream_t s) : s_(s)
+    {
+        for (auto &e : ev_)
+            HUB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    ~Engine() override
+    {
+        (void)hipStreamSynchronize(s_);
+        for (auto &e : ev_)
+            (void)hipEventDestroy(e);
+    }
 
-    int active() const override { return (int)active_.size(); }
+    int active() const override
+    {
+        int n = 0;
+        for (const auto &sl : slots_)
+            n += !sl->done;
+        return n;
+    }
 
     void add(hubbard *h, const hubbard_opts &o, hubbard_result *res) override
     {
@@ -80,95 +101,90 @@ class Engine : public BatchRunner {
         sl->t0 = std::chrono::steady_clock::now();
         const int64_t n = h->dim;
         sl->work = std::make_unique<Dev>(2 * sizeof(T) * (size_t)n);
-        sl->scal = std::make_unique<Dev>(8 * sizeof(double));
+        sl->state = std::make_unique<Dev>(sizeof(BatchState));
+        sl->hist = std::make_unique<Dev>(sizeof(double) * 2 * (size_t)o.max_iter);
         sl->rpi = rows_per_item(h);
         sl->nitems = (int)((h->up.dim + sl->rpi - 1) / sl->rpi);
         const int sb = stream_blocks(n);
         sl->part = std::make_unique<Dev>(sizeof(double) * (size_t)std::max(sl->nitems, 2 * sb + 8));
         // f_1 from the seed (or the given vector), normalised in FP64 (Alg. 1)
         double *part = static_cast<double *>(sl->part->p);
-        double *S = static_cast<double *>(sl->scal->p);
+        BatchState *st = static_cast<BatchState *>(sl->state->p);
         launch_start_norm2(o.start, o.seed, n, part, sb, s_);
-        launch_reduce(part, sb, 0, 1, S + 4, s_);
+        launch_reduce(part, sb, 0, 1, st->S + 4, s_);
         double nrm2 = 0.0;
-        HUB_HIP(hipMemcpyAsync(&nrm2, S + 4, sizeof(double), hipMemcpyDeviceToHost, s_));
+        HUB_HIP(hipMemcpyAsync(&nrm2, st->S + 4, sizeof(double), hipMemcpyDeviceToHost, s_));
         HUB_HIP(hipStreamSynchronize(s_));
         if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
             fail(HUBBARD_EINVAL, "start vector has zero or non-finite norm");
         T *v0 = static_cast<T *>(sl->work->p);
         launch_start_fill<T>(o.start, o.seed, 1.0 / std::sqrt(nrm2), v0, v0 + n, h->up.dim, h->dn.dim, h->dn.dim, s_);
-        launch_init_scalars(S, s_);
-        active_.push_back(std::move(sl));
+        launch_batch_init_state(st, s_);
+        slots_.push_back(std::move(sl));
         dirty_ = true;
     }
 
-    bool empty() const { return active_.empty(); }
+    bool empty() const { return active() == 0; }
 
-    // One Lanczos step for every active instance; finished ones are finalised
-    // and removed.
+    // Launches one more step of every active instance (instances that stopped
+    // on the device skip it) and reads back the mailboxes of the steps that
+    // are more than kLookahead behind; returns the instances found finished.
     std::vector<hubbard_result *> step() override
     {
         std::vector<hubbard_result *> finished;
-        if (active_.empty())
-            return finished;
         if (dirty_)
-            rebuild();
-        const int n = (int)active_.size();
-        launch_batch_step<T>(static_cast<BatchInst *>(insts_->p), n, static_cast<const BatchItem *>(items_->p),
-                             n_items_, lds_, static_cast<double *>(mail_->p), s_);
-        HUB_HIP(hipMemcpyAsync(mail_host_->p, mail_->p, sizeof(double) * 2 * (size_t)n, hipMemcpyDeviceToHost, s_));
-        HUB_HIP(hipStreamSynchronize(s_));
-        const double *mb = static_cast<const double *>(mail_host_->p);
-        bool any_done = false;
-        for (int i = 0; i < n; i++) {
-            Slot<T> &sl = *active_[(size_t)i];
-            sl.cur ^= 1;
-            if (check(sl, mb[2 * i], mb[2 * i + 1])) {
-                finalize(sl);
-                finished.push_back(sl.res);
-                any_done = true;
-            }
+            rebuild(finished);
+        if (table_.empty())
+            return finished;
+        if (pending_stopped_ < (int)table_.size()) {
+            const int k = (int)(launched_ % kRing);
+            double *mb = static_cast<double *>(mail_->p) + (size_t)k * 4 * table_.size();
+            launch_batch_step<T>(static_cast<BatchInst *>(insts_->p), (int)table_.size(),
+                                 static_cast<const BatchItem *>(items_->p), n_items_, lds_, mb, s_);
+            double *mh = static_cast<double *>(mail_host_->p) + (size_t)k * 4 * table_.size();
+            HUB_HIP(hipMemcpyAsync(mh, mb, sizeof(double) * 4 * table_.size(), hipMemcpyDeviceToHost, s_));
+            HUB_HIP(hipEventRecord(ev_[k], s_));
+            launched_++;
         }
-        if (any_done) {
-            std::vector<std::unique_ptr<Slot<T>>> keep;
-            for (auto &sl : active_)
-                if (!sl->done)
-                    keep.push_back(std::move(sl));
-            active_.swap(keep);
+        // read back what is kLookahead steps old, or everything when every
+        // instance has stopped on the device
+        while (read_ < launched_ && (launched_ - read_ > kLookahead || pending_stopped_ == (int)table_.size()))
+            read_step(finished);
+        if (read_ == launched_ && pending_stopped_ == (int)table_.size()) {
+            // every instance in the table is finished: the next step starts a fresh table
             dirty_ = true;
         }
         return finished;
     }
 
   private:
-    // the energy test of Sec. 2.2 and the breakdown rule, as in the single-instance driver
-    bool check(Slot<T> &sl, double a, double b)
+    static constexpr int kRing = kLookahead + 2;
+
+    void read_step(std::vector<hubbard_result *> &finished)
     {
-        if (!std::isfinite(a) || !std::isfinite(b))
-            fail(HUBBARD_EDEVICE, "non-finite Lanczos coefficient in a batched solve");
-        sl.a.push_back(a);
-        sl.b.push_back(b);
-        const int j = (int)sl.a.size();
-        const double e = tridiag_lowest(sl.a.data(), sl.b.data(), j);
-        sl.e.push_back(e);
-        if (sl.o.tol >= 0.0 && j >= 2 && std::fabs(e - sl.e[(size_t)j - 2]) <= sl.o.tol * std::fmax(1.0, std::fabs(e))) {
-            sl.stop = HUBBARD_STOP_CONVERGED;
-            return true;
+        const int k = (int)(read_ % kRing);
+        HUB_HIP(hipEventSynchronize(ev_[k]));
+        const double *mb = static_cast<const double *>(mail_host_->p) + (size_t)k * 4 * table_.size();
+        for (size_t i = 0; i < table_.size(); i++) {
+            Slot<T> &sl = *table_[i];
+            if (sl.done)
+                continue;
+            const double code = mb[4 * i + 3];
+            if (code == kMailStopped)
+                continue;
+            if (code == kMailBad)
+                fail(HUBBARD_EDEVICE, "non-finite Lanczos coefficient in a batched solve");
+            sl.a.push_back(mb[4 * i]);
+            sl.b.push_back(mb[4 * i + 1]);
+            sl.e.push_back(mb[4 * i + 2]);
+            if (code != kMailRunning) {
+                sl.stop = (int)code;
+                finalize(sl);
+                finished.push_back(sl.res);
+                pending_stopped_++;
+            }
         }
-        sl.scale = std::fmax(sl.scale, std::fabs(a) + (j > 1 ? sl.b[(size_t)j - 2] : 0.0));
-        if (b == 0.0 || b <= 1e-12 * sl.scale) {
-            sl.stop = HUBBARD_STOP_BREAKDOWN;
-            return true;
-        }
-        if ((int64_t)j >= sl.h->dim) {
-            sl.stop = HUBBARD_STOP_EXHAUSTED;
-            return true;
-        }
-        if (j >= sl.o.max_iter) {
-            sl.stop = HUBBARD_STOP_MAXITER;
-            return true;
-        }
-        return false;
+        read_++;
     }
 
     void finalize(Slot<T> &sl)
@@ -199,14 +215,31 @@ class Engine : public BatchRunner {
         *sl.res = r;
     }
 
-    void rebuild()
+    // New descriptor table: waits for the steps in flight, reads their
+    // mailboxes, drops finished instances (their buffers are free to go once
+    // no step in flight refers to them) and lists the work items of the rest.
+    void rebuild(std::vector<hubbard_result *> &finished)
     {
-        const int n = (int)active_.size();
+        HUB_HIP(hipStreamSynchronize(s_));
+        while (read_ < launched_)
+            read_step(finished);
+        std::vector<std::unique_ptr<Slot<T>>> keep;
+        for (auto &sl : slots_)
+            if (!sl->done)
+                keep.push_back(std::move(sl));
+        slots_.swap(keep);
+        table_.clear();
+        launched_ = read_ = 0;
+        pending_stopped_ = 0;
+        dirty_ = false;
+        const int n = (int)slots_.size();
+        if (n == 0)
+            return;
         std::vector<BatchInst> desc((size_t)n);
         std::vector<BatchItem> items;
         size_t lds = 16;
         for (int i = 0; i < n; i++) {
-            Slot<T> &sl = *active_[(size_t)i];
+            Slot<T> &sl = *slots_[(size_t)i];
             const hubbard *h = sl.h;
             BatchInst &d = desc[(size_t)i];
             std::memset(&d, 0, sizeof(d));
@@ -218,6 +251,7 @@ class Engine : public BatchRunner {
             d.nnz_dn = h->dev.nnz_dn;
             d.dim_up = h->up.dim;
             d.dim_dn = h->dn.dim;
+            d.dim = h->dim;
             d.w_up = std::max(1, h->up.width);
             d.w_dn = h->dn.width;
             d.t = h->t;
@@ -225,11 +259,14 @@ class Engine : public BatchRunner {
             T *v0 = static_cast<T *>(sl.work->p);
             d.vec0 = v0;
             d.vec1 = v0 + h->dim;
-            d.S = static_cast<double *>(sl.scal->p);
+            d.st = static_cast<BatchState *>(sl.state->p);
+            d.hist = static_cast<double *>(sl.hist->p);
             d.part = static_cast<double *>(sl.part->p);
+            d.tol = sl.o.tol;
             d.nparts = sl.nitems;
-            d.cur = sl.cur;
             d.slot = i;
+            d.max_iter = sl.o.max_iter;
+            sl.index = i;
             for (int k = 0; k < sl.nitems; k++) {
                 BatchItem it;
                 it.inst = i;
@@ -239,12 +276,13 @@ class Engine : public BatchRunner {
                 items.push_back(it);
             }
             lds = std::max(lds, (size_t)h->dn.dim * sizeof(T));
+            table_.push_back(&sl);
         }
         if (!insts_ || insts_cap_ < (size_t)n) {
             insts_cap_ = (size_t)n * 2;
             insts_ = std::make_unique<Dev>(sizeof(BatchInst) * insts_cap_);
-            mail_ = std::make_unique<Dev>(sizeof(double) * 2 * insts_cap_);
-            mail_host_ = std::make_unique<Pinned>(sizeof(double) * 2 * insts_cap_);
+            mail_ = std::make_unique<Dev>(sizeof(double) * 4 * insts_cap_ * kRing);
+            mail_host_ = std::make_unique<Pinned>(sizeof(double) * 4 * insts_cap_ * kRing);
         }
         if (!items_ || items_cap_ < items.size()) {
             items_cap_ = items.size() * 2;
@@ -255,15 +293,18 @@ class Engine : public BatchRunner {
         HUB_HIP(hipStreamSynchronize(s_));
         n_items_ = (int)items.size();
         lds_ = lds;
-        dirty_ = false;
     }
 
     hipStream_t s_;
-    std::vector<std::unique_ptr<Slot<T>>> active_;
+    std::vector<std::unique_ptr<Slot<T>>> slots_;
+    std::vector<Slot<T> *> table_;  // the instances of the current descriptor table, in slot order
     std::unique_ptr<Dev> insts_, items_, mail_;
     std::unique_ptr<Pinned> mail_host_;
+    hipEvent_t ev_[kRing];
     size_t insts_cap_ = 0, items_cap_ = 0, lds_ = 16;
     int n_items_ = 0;
+    int64_t launched_ = 0, read_ = 0;  // steps launched and read back since the last rebuild
+    int pending_stopped_ = 0;         // instances of the table found finished
     bool dirty_ = true;
 };
 

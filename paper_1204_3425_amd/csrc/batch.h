@@ -8,21 +8,43 @@
 
 namespace hub {
 
+// Per-instance state that the batched kernels update in place (device memory,
+// owned by the instance; descriptors stay read-only between rebuilds).
+struct BatchState {
+    double S[8];     // {1/s of the current vector, alpha, beta, c, -, -, a_j, b_{j+1}}
+    double scale;    // running max_k |a_k| + b_k (breakdown test)
+    double e_prev;   // Ritz value of the previous step
+    int32_t j;       // steps done
+    int32_t stopped; // set by the step that stops the instance
+    int32_t cur;     // 0: vec0 holds s f_j, 1: vec1 does
+    int32_t pad_;
+};
+
 // One instance as the batched kernels see it (plain data, device memory).
 struct BatchInst {
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
-    int64_t dim_up, dim_dn;
+    int64_t dim_up, dim_dn, dim;
     int32_t w_up, w_dn;
     double t, U;
     void *vec0, *vec1;  // the two Lanczos vectors, dense rows
-    double *S;          // {1/s of the current vector, alpha, beta, c, -, -, a_j, b_{j+1}}
+    BatchState *st;
+    double *hist;       // a_{k+1} at 2k, b_{k+2} at 2k + 1
     double *part;       // partial sums, one per work item of this instance
+    double tol;
     int32_t nparts;
-    int32_t cur;        // 0: vec0 holds s f_j, 1: vec1 does
     int32_t slot;       // mailbox slot
+    int32_t max_iter;
     int32_t pad_;
 };
+
+// Mailbox entry written by the step's last kernel for every instance:
+// {a_j, b_{j+1}, E_j, code}; code = -1 running, a HUBBARD_STOP_* value when
+// this step stops the instance, kMailStopped when it had stopped before,
+// kMailBad when a coefficient is not finite.
+constexpr double kMailRunning = -1.0;
+constexpr double kMailStopped = -2.0;
+constexpr double kMailBad = -3.0;
 
 // A work item: rows [r0, r0 + nrows) of instance `inst`, writing partial `part`.
 struct BatchItem {
@@ -35,6 +57,9 @@ struct BatchItem {
 template <typename T>
 void launch_batch_step(BatchInst *insts_dev, int n_inst, const BatchItem *items_dev, int n_items, size_t lds_bytes,
                        double *mailbox_dev, hipStream_t s);
+
+// zeroes an instance's state and sets S = {1, 1, 0, 0} (f_1 has scale 1, b_1 = 0)
+void launch_batch_init_state(BatchState *st, hipStream_t s);
 
 // Largest sector the batched kernels take: a row must fit in 64 KB of LDS.
 bool batchable(const hubbard *h, int precision);
@@ -50,7 +75,9 @@ class BatchRunner {
     // allocates the instance's vectors and writes its start vector; res is
     // written when the instance finishes
     virtual void add(hubbard *h, const hubbard_opts &o, hubbard_result *res) = 0;
-    // one Lanczos step of every active instance; returns the results finished in it
+    // launches one more Lanczos step of every active instance and returns the
+    // results that finished in steps the host has read back (the host reads
+    // the step mailboxes a few steps behind the device)
     virtual std::vector<hubbard_result *> step() = 0;
     virtual int active() const = 0;
 };

@@ -7,10 +7,13 @@
 //     batched H.v + three-term update  (work item = rows of one instance)
 //     per-instance reduction -> a_j
 //     batched q - a_j f_j + partial norms
-//     per-instance reduction -> b_{j+1}
+//     per-instance reduction -> b_{j+1}, the Ritz value E_j of T_j and the
+//                               stop test of the single-instance driver
 // Work items never span two instances and each instance's partial sums are
 // added in a fixed order, so an instance's results do not depend on which
-// other instances share the launches.
+// other instances share the launches.  An instance that has stopped skips
+// every kernel of later steps, so the host can read the step mailboxes a few
+// steps behind without holding the device.
 //
 // H.v here is the one-pass form: a workgroup stages each row of its work item
 // in LDS, gathers the down-spin hops from it and adds the up-spin rows from
@@ -51,10 +54,14 @@ __global__ __launch_bounds__(kThreads) void batch_hv_kernel(const BatchInst *__r
     __shared__ double red[kThreads / 64];
     const BatchItem it = items[blockIdx.x];
     const BatchInst &in = insts[it.inst];
+    const BatchState *st = in.st;
+    if (st->stopped)
+        return;
     const int64_t ddn = in.dim_dn;
-    const T *__restrict__ x = reinterpret_cast<const T *>(in.cur ? in.vec1 : in.vec0);
-    T *__restrict__ y = reinterpret_cast<T *>(in.cur ? in.vec0 : in.vec1);
-    const double alpha = in.S[1], beta = in.S[2];
+    const int cur = st->cur;
+    const T *__restrict__ x = reinterpret_cast<const T *>(cur ? in.vec1 : in.vec0);
+    T *__restrict__ y = reinterpret_cast<T *>(cur ? in.vec0 : in.vec1);
+    const double alpha = st->S[1], beta = st->S[2];
     const T a_s = (T)alpha, b_s = (T)beta, tp = (T)in.t, tm = (T)(-in.t), U = (T)in.U;
     double acc = 0.0;
     for (int64_t r = it.r0; r < it.r0 + it.nrows; r++) {
@@ -96,9 +103,13 @@ __global__ __launch_bounds__(kThreads) void batch_axpy_kernel(const BatchInst *_
     __shared__ double red[kThreads / 64];
     const BatchItem it = items[blockIdx.x];
     const BatchInst &in = insts[it.inst];
-    const T *__restrict__ v = reinterpret_cast<const T *>(in.cur ? in.vec1 : in.vec0);
-    T *__restrict__ w = reinterpret_cast<T *>(in.cur ? in.vec0 : in.vec1);
-    const T c = (T)in.S[3];
+    const BatchState *st = in.st;
+    if (st->stopped)
+        return;
+    const int cur = st->cur;
+    const T *__restrict__ v = reinterpret_cast<const T *>(cur ? in.vec1 : in.vec0);
+    T *__restrict__ w = reinterpret_cast<T *>(cur ? in.vec0 : in.vec1);
+    const T c = (T)st->S[3];
     const int64_t i0 = it.r0 * in.dim_dn, i1 = (it.r0 + it.nrows) * in.dim_dn;
     double acc = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
@@ -111,36 +122,165 @@ __global__ __launch_bounds__(kThreads) void batch_axpy_kernel(const BatchInst *_
         in.part[it.part] = s;
 }
 
+// Number of negative pivots of the LDL^T factorisation of T_m - x I (T_m:
+// diagonal hist[0], hist[2], ..., off-diagonal hist[1], hist[3], ...), which
+// by Sylvester's law of inertia is the number of eigenvalues of T_m below x.
+__device__ int negative_pivots(const double *__restrict__ hist, int m, double x)
+{
+    const double floor_piv = 1e-290;
+    double piv = hist[0] - x;
+    if (fabs(piv) < floor_piv)
+        piv = -floor_piv;
+    int neg = piv < 0.0;
+    for (int i = 1; i < m; i++) {
+        const double e = hist[2 * i - 1];
+        piv = (hist[2 * i] - x) - e * (e / piv);
+        if (fabs(piv) < floor_piv)
+            piv = -floor_piv;
+        neg += piv < 0.0;
+    }
+    return neg;
+}
+
+// Lowest eigenvalue of T_m by multisection: every thread of the workgroup
+// counts the eigenvalues below one of blockDim.x points of the bracket
+// [lo, hi] (no eigenvalue below lo, at least one below hi), and the bracket
+// shrinks to the two points around the first count above zero, until no point
+// falls strictly inside it.  Returns hi, as the host's bisection does.
+__device__ double lowest_eigenvalue(const double *__restrict__ hist, int m, double *sh, int *first)
+{
+    if (threadIdx.x == 0) {
+        double lo = hist[0], hi = hist[0];
+        for (int i = 0; i < m; i++) {
+            const double rad = (i > 0 ? fabs(hist[2 * i - 1]) : 0.0) + (i < m - 1 ? fabs(hist[2 * i + 1]) : 0.0);
+            lo = fmin(lo, hist[2 * i] - rad);
+            hi = fmax(hi, hist[2 * i] + rad);
+        }
+        const double pad = 0x1p-52 * (fabs(lo) + fabs(hi)) + 1e-290;
+        sh[0] = lo - pad;
+        sh[1] = hi + pad;
+    }
+    __syncthreads();
+    const int nt = (int)blockDim.x;
+    for (int round = 0; round < 64; round++) {
+        const double lo = sh[0], hi = sh[1];
+        auto point = [&](int t) { return fmin(hi, fmax(lo, lo + (hi - lo) * ((double)(t + 1) / (double)(nt + 1)))); };
+        const double x = point((int)threadIdx.x);
+        const int c = negative_pivots(hist, m, x);
+        if (threadIdx.x == 0)
+            *first = nt;
+        __syncthreads();
+        if (c > 0)
+            atomicMin(first, (int)threadIdx.x);
+        __syncthreads();
+        const int f = *first;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double nlo = f == 0 ? lo : point(f - 1);
+            const double nhi = f == nt ? hi : point(f);
+            sh[2] = (nlo == lo && nhi == hi) ? 1.0 : 0.0;
+            sh[0] = nlo;
+            sh[1] = nhi;
+        }
+        __syncthreads();
+        if (sh[2] != 0.0)
+            break;
+    }
+    return sh[1];
+}
+
 // One workgroup per instance: fixed-order sum of its partials, then the same
-// scalar updates as the single-instance driver (a_j after the H.v, b_{j+1}
-// and the next step's alpha, beta after the update).  The step's (a, b) is
-// also written to the instance's slot of the mailbox the host reads, and the
-// two vectors swap roles (the updated q holds b_{j+1} f_{j+1}).
-__global__ __launch_bounds__(kThreads) void batch_reduce_kernel(BatchInst *__restrict__ insts, int mode,
+// scalar updates as the single-instance driver.  mode 0 (after the H.v): a_j.
+// mode 1 (after the update): b_{j+1}, the next step's alpha and beta, E_j, the
+// energy, breakdown, exhausted-space and iteration-count tests in the
+// single-instance driver's order, and the step's mailbox entry; the two
+// vectors swap roles (the updated q holds b_{j+1} f_{j+1}).
+__global__ __launch_bounds__(kThreads) void batch_reduce_kernel(const BatchInst *__restrict__ insts, int mode,
                                                                 double *__restrict__ mailbox)
 {
     __shared__ double red[kThreads / 64];
-    BatchInst &in = insts[blockIdx.x];
+    __shared__ double sh[4];
+    __shared__ int first;
+    const BatchInst &in = insts[blockIdx.x];
+    BatchState *st = in.st;
+    if (st->stopped) {
+        if (mode == 1 && threadIdx.x == 0)
+            mailbox[4 * in.slot + 3] = kMailStopped;
+        return;
+    }
     double acc = 0.0;
     for (int i = threadIdx.x; i < in.nparts; i += blockDim.x)
         acc += in.part[i];
     const double s = wg_sum(acc, red);
-    if (threadIdx.x == 0) {
-        double *S = in.S;
-        if (mode == 0) {
+    double *S = st->S;
+    if (mode == 0) {
+        if (threadIdx.x == 0) {
             const double a = s * S[0];
             S[3] = a * S[0];
             S[6] = a;
-        } else {
-            const double b = sqrt(s);
-            S[7] = b;
-            S[2] = -b * S[0];
-            S[0] = b > 0.0 ? 1.0 / b : 0.0;
-            S[1] = S[0];
-            mailbox[2 * in.slot] = S[6];
-            mailbox[2 * in.slot + 1] = b;
-            in.cur ^= 1;
         }
+        return;
+    }
+    const int j0 = st->j;  // 0-based step index
+    if (threadIdx.x == 0) {
+        const double b = sqrt(s);
+        S[7] = b;
+        in.hist[2 * j0] = S[6];
+        in.hist[2 * j0 + 1] = b;
+    }
+    __syncthreads();
+    const double a = S[6], b = S[7];
+    const int m = j0 + 1;
+    double code = kMailRunning;
+    double e = 0.0;
+    if (!isfinite(a) || !isfinite(b)) {
+        code = kMailBad;
+    } else {
+        e = lowest_eigenvalue(in.hist, m, sh, &first);
+    }
+    if (threadIdx.x == 0) {
+        if (code == kMailRunning) {
+            if (in.tol >= 0.0 && m >= 2 && fabs(e - st->e_prev) <= in.tol * fmax(1.0, fabs(e))) {
+                code = HUBBARD_STOP_CONVERGED;
+            } else {
+                st->scale = fmax(st->scale, fabs(a) + (m > 1 ? in.hist[2 * j0 - 1] : 0.0));
+                if (b == 0.0 || b <= 1e-12 * st->scale)
+                    code = HUBBARD_STOP_BREAKDOWN;
+                else if ((int64_t)m >= in.dim)
+                    code = HUBBARD_STOP_EXHAUSTED;
+                else if (m >= in.max_iter)
+                    code = HUBBARD_STOP_MAXITER;
+            }
+        }
+        st->e_prev = e;
+        st->j = m;
+        S[2] = -b * S[0];
+        S[0] = b > 0.0 ? 1.0 / b : 0.0;
+        S[1] = S[0];
+        st->cur ^= 1;
+        if (code != kMailRunning)
+            st->stopped = 1;
+        double *mb = mailbox + 4 * in.slot;
+        mb[0] = a;
+        mb[1] = b;
+        mb[2] = e;
+        mb[3] = code;
+    }
+}
+
+__global__ void batch_init_state_kernel(BatchState *st)
+{
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 8; k++)
+            st->S[k] = 0.0;
+        st->S[0] = 1.0;
+        st->S[1] = 1.0;
+        st->scale = 0.0;
+        st->e_prev = 0.0;
+        st->j = 0;
+        st->stopped = 0;
+        st->cur = 0;
+        st->pad_ = 0;
     }
 }
 
@@ -165,5 +305,11 @@ void launch_batch_step(BatchInst *insts_dev, int n_inst, const BatchItem *items_
 
 template void launch_batch_step<double>(BatchInst *, int, const BatchItem *, int, size_t, double *, hipStream_t);
 template void launch_batch_step<float>(BatchInst *, int, const BatchItem *, int, size_t, double *, hipStream_t);
+
+void launch_batch_init_state(BatchState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_init_state_kernel, dim3(1), dim3(64), 0, s, st);
+    HUB_HIP(hipGetLastError());
+}
 
 }  // namespace hub

@@ -455,6 +455,36 @@ def test_batch_result_independent_of_mix():
         assert alone["E0"] == mix[k]["E0"]
 
 
+def test_batch_stop_rules_match_single_instance():
+    """The batched stop tests (computed on the device) against the single-
+    instance driver: a 1-state sector (breakdown at once), the dimer, a 9-state
+    sector that exhausts its Krylov space, a fixed step count (tol < 0) and an
+    iteration cap, in one batch."""
+    probs = [workload.problem("one_state", 4, workload.ring(4), 4, 0, 1.0, 2.0),
+             workload.problem("dimer", 2, [(0, 1)], 1, 1, 1.0, 4.0),
+             workload.problem("tiny3", 3, workload.ring(3), 1, 1, 1.0, 1.0),
+             workload.ring8(), workload.ring8()]
+    hs = [_build(p) for p in probs]
+    opts = [(1e-12, 50), (1e-12, 50), (1e-12, 50), (-1.0, 37), (1e-14, 12)]
+    got = []
+    for (tol, mi), h, p in zip(opts, hs, probs):
+        got.append(hb.hubbard_lanczos_batch([h], tol=tol, max_iter=mi, precision=hb.HUBBARD_FP64,
+                                            seeds=[p.seed], history=True)[0])
+    mixed = [hb.hubbard_lanczos_batch(hs, tol=opts[0][0], max_iter=50, precision=hb.HUBBARD_FP64,
+                                      seeds=[p.seed for p in probs], history=True)]
+    for (tol, mi), h, p, g in zip(opts, hs, probs, got):
+        solo = _lanczos_gpu(h, p, hb.HUBBARD_FP64, tol, mi)
+        assert g["stop"] == solo["stop"], p.name
+        assert g["n_iter"] == solo["n_iter"], p.name
+        assert g["E0"] == pytest.approx(solo["E0"], rel=1e-12, abs=1e-13), p.name
+        assert np.allclose(g["a"], solo["a"], rtol=1e-12, atol=1e-13)
+    assert got[3]["stop"] == "max_iter" and got[3]["n_iter"] == 37
+    assert got[4]["stop"] == "max_iter" and got[4]["status"] == hb.HUBBARD_ENOCONV
+    # the first three again inside one batch with the others
+    for k in range(3):
+        assert mixed[0][k]["E0"] == got[k]["E0"] and mixed[0][k]["n_iter"] == got[k]["n_iter"]
+
+
 def test_batch_with_psi_requests_and_large_rows():
     """Solves that ask for psi, or whose rows exceed the batched kernels' LDS,
     run on the single-instance path inside the same call."""
