@@ -275,7 +275,7 @@ class Engine : public BatchRunner {
                 it.nrows = std::min<int64_t>(sl.rpi, h->up.dim - it.r0);
                 items.push_back(it);
             }
-            lds = std::max(lds, (size_t)h->dn.dim * sizeof(T));
+            lds = std::max(lds, (size_t)sl.rpi * (size_t)h->dn.dim * sizeof(T));  // one work item's rows
             table_.push_back(&sl);
         }
         if (!insts_ || insts_cap_ < (size_t)n) {

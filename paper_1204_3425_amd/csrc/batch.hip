@@ -15,8 +15,8 @@
 // every kernel of later steps, so the host can read the step mailboxes a few
 // steps behind without holding the device.
 //
-// H.v here is the one-pass form: a workgroup stages each row of its work item
-// in LDS, gathers the down-spin hops from it and adds the up-spin rows from
+// H.v here is the one-pass form: a workgroup stages the rows of its work item
+// in LDS, gathers the down-spin hops from them and adds the up-spin rows from
 // global memory (every vector of a batched instance is small enough to stay in
 // the L2 and the Infinity Cache).
 #include <hip/hip_runtime.h>
@@ -45,6 +45,12 @@ __device__ inline double wg_sum(double v, double *scratch)
 
 constexpr int kThreads = 256;
 
+// The work item's rows are staged in LDS at once (each thread issues eight
+// loads before its first LDS write); then the item's elements are spread over
+// all threads, row by row, so short rows leave no lane idle.  A thread keeps
+// its position (r, d) and steps it by the workgroup size.  Down-spin hops read
+// LDS, with a column's table entries loaded eight at a time before the
+// gathers; up-spin hops read the other rows from global memory, four at a time.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void batch_hv_kernel(const BatchInst *__restrict__ insts,
                                                             const BatchItem *__restrict__ items)
@@ -57,39 +63,71 @@ __global__ __launch_bounds__(kThreads) void batch_hv_kernel(const BatchInst *__r
     const BatchState *st = in.st;
     if (st->stopped)
         return;
-    const int64_t ddn = in.dim_dn;
+    const int ddn = (int)in.dim_dn;
+    const int n = (int)(it.nrows * in.dim_dn);  // elements of the item (at most 16384)
     const int cur = st->cur;
     const T *__restrict__ x = reinterpret_cast<const T *>(cur ? in.vec1 : in.vec0);
     T *__restrict__ y = reinterpret_cast<T *>(cur ? in.vec0 : in.vec1);
     const double alpha = st->S[1], beta = st->S[2];
     const T a_s = (T)alpha, b_s = (T)beta, tp = (T)in.t, tm = (T)(-in.t), U = (T)in.U;
+    const int64_t base = it.r0 * in.dim_dn;
+    for (int i0 = 0; i0 < n; i0 += 8 * kThreads) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int i = i0 + u * kThreads + (int)threadIdx.x;
+            v[u] = i < n ? x[base + i] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int i = i0 + u * kThreads + (int)threadIdx.x;
+            if (i < n)
+                xs[i] = v[u];
+        }
+    }
+    __syncthreads();
     double acc = 0.0;
-    for (int64_t r = it.r0; r < it.r0 + it.nrows; r++) {
-        const T *__restrict__ xr = x + r * ddn;
-        for (int64_t d = threadIdx.x; d < ddn; d += blockDim.x)
-            xs[d] = xr[d];
-        __syncthreads();
-        const uint32_t su = in.states_up[r];
+    int rl = (int)threadIdx.x / ddn, d = (int)threadIdx.x - rl * ddn;
+    for (int i = (int)threadIdx.x; i < n; i += kThreads) {
+        const int64_t r = it.r0 + rl;
+        const T xv = xs[i];
+        const T *__restrict__ xrow = xs + (int64_t)rl * ddn;
+        T h = U * (T)__popc(in.states_up[r] & in.states_dn[d]) * xv;
+        const int nd = in.nnz_dn[d];
+        for (int k0 = 0; k0 < nd; k0 += 8) {
+            uint32_t e[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                e[u] = k0 + u < nd ? in.dn_cols[(int64_t)(k0 + u) * ddn + d] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (k0 + u < nd)
+                    h = fma((e[u] >> 31) ? tp : tm, xrow[e[u] & 0x7fffffffu], h);
+        }
         const int nu = in.nnz_up[r];
         const uint32_t *__restrict__ urow = in.up_rows + r * in.w_up;
-        for (int64_t d = threadIdx.x; d < ddn; d += blockDim.x) {
-            const T xv = xs[d];
-            T h = U * (T)__popc(su & in.states_dn[d]) * xv;
-            const int nd = in.nnz_dn[d];
-            for (int k = 0; k < nd; k++) {
-                const uint32_t e = in.dn_cols[(int64_t)k * ddn + d];
-                h = fma((e >> 31) ? tp : tm, xs[e & 0x7fffffffu], h);
+        for (int k0 = 0; k0 < nu; k0 += 4) {
+            T v[4];
+            uint32_t e[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                e[u] = k0 + u < nu ? urow[k0 + u] : 0u;
+                v[u] = k0 + u < nu ? x[(int64_t)(e[u] & 0x7fffffffu) * ddn + d] : (T)0;
             }
-            for (int k = 0; k < nu; k++) {
-                const uint32_t e = urow[k];
-                h = fma((e >> 31) ? tp : tm, x[(int64_t)(e & 0x7fffffffu) * ddn + d], h);
-            }
-            const int64_t J = r * ddn + d;
-            const T q = a_s * h + b_s * y[J];
-            y[J] = q;
-            acc += (double)q * (double)xv;
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (k0 + u < nu)
+                    h = fma((e[u] >> 31) ? tp : tm, v[u], h);
         }
-        __syncthreads();
+        const int64_t J = base + i;
+        const T q = a_s * h + b_s * y[J];
+        y[J] = q;
+        acc += (double)q * (double)xv;
+        d += kThreads;
+        while (d >= ddn) {
+            d -= ddn;
+            rl++;
+        }
     }
     const double s = wg_sum(acc, red);
     if (threadIdx.x == 0)
