@@ -176,10 +176,14 @@ int hubbard_start_raw(uint64_t seed, int64_t dim, double *f, void *hip_stream);
  * current device, writing res[i].  Solves without a psi request whose rows fit
  * in 64 KB share their launches: every step of every such solve runs in the
  * same four kernel launches (Sec. 5 notes that small systems leave the GPU
- * idle).  The others run one after another.  A batched result does not depend
- * on which other solves share the batch, and agrees with the same solve run
- * alone within rounding.  Synchronous; the stream of hs[0] is used.  Returns the
- * most severe per-solve status. */
+ * idle), and the Ritz value E_j and the stop tests of hubbard_lanczos_ex are
+ * evaluated on the device, so the host reads results a few steps behind.  The
+ * others run one after another.  A batched result does not depend on which
+ * other solves share the batch, and agrees with the same solve run alone
+ * within rounding (the batched E_j comes from a multisection on the device,
+ * the single-instance one from a bisection on the host).  res[i].err_est is
+ * the Lanczos estimate b_{m+1} |y_m| / max(1, |E0|).  Synchronous; the stream
+ * of hs[0] is used.  Returns the most severe per-solve status. */
 int hubbard_lanczos_batch(hubbard_h *hs, int n, const hubbard_opts *opts, hubbard_result *res);
 
 /* ---------------------------------------------------------------- serving

@@ -37,17 +37,22 @@ struct Job {
     hubbard_completion done{};
 };
 
-// Upper bound of the device bytes a request needs: work vectors (two, plus
-// partial sums) and tables (at most n_edges entries per row).
+// Upper bound of the device bytes a request needs: the two work vectors on
+// padded rows, partial sums, the batched engine's coefficient history, and the
+// tables with at most n_edges entries per row: up side (row-major entries,
+// blocked entries, one 32-slot line, counts, states) and down side
+// (column-major entries, 64- and 32-bit offset groups, 16-bit groups, counts,
+// states).
 size_t footprint(const hubbard_request &r)
 {
     const uint64_t du = binomial(r.sites, r.n_up), dd = binomial(r.sites, r.n_dn);
     const size_t es = r.precision == HUBBARD_FP64 ? 8 : 4;
     const size_t ld = (size_t)((dd + 63) / 64 * 64);
-    const size_t vecs = 2 * es * (size_t)du * ld + 64 * 1024;
+    const size_t vecs = 2 * es * (size_t)du * ld + 64 * 1024 + 16 * (size_t)std::max(1, r.max_iter);
     const size_t w = (size_t)std::max(1, r.n_edges);
-    const size_t tables = (size_t)du * (w * 4 + 6) + (size_t)dd * (w * 4 * 3 + 7);
-    return vecs + tables;
+    const size_t up = (size_t)du * (8 * w + 142);
+    const size_t dn = (size_t)dd * (14 * w + 56);
+    return vecs + up + dn;
 }
 
 }  // namespace
