@@ -177,6 +177,22 @@ def test_apply_4x4_sampled_rows(precision):
     assert abs(lhs - rhs) <= tol * (np.abs(u).sum() + np.abs(x).sum())
 
 
+def test_apply_ring16_sampled_rows():
+    """The 16-site ring at half filling (dim 165,636,900, 16-hop rows: a
+    different table structure from the 4x4 lattice at the same size), FP64 on
+    padded rows, checked on 2000 sampled rows."""
+    p = workload.problem("ring16", 16, workload.ring(16), 8, 8, 1.0, 6.0)
+    _say("apply ring16 sampled")
+    h = _build(p)
+    m = _oracle(p)
+    x = workload.random_vector(p.dim, p.seed + 5)
+    got = _apply_gpu_ld(h, x, hb.HUBBARD_FP64)
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([[0, p.dim - 1, p.dim_dn - 1], rng.integers(0, p.dim, 2000)])
+    ref = m.apply_rows(x, rows)
+    assert np.abs(got[rows] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
 @pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("pad", [0, 3, 64])
 def test_apply_strided_rows_equal_dense(precision, pad):
