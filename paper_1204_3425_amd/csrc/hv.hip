@@ -512,11 +512,14 @@ struct LineArgs {
 // Blocked slab pass, line layout (rows of at most 32 hops).  Same workgroup
 // numbering and LDS staging as hv_blocks_kernel, plus a zero row after the
 // block that padding hops point at.  A row's entries are one 128-byte line
-// (internal hops from the front, external from the back), so each lane
-// group loads them with eight independent loads issued together with the
-// running output, and the hop counts come in one word.  Internal hops are
-// summed with the sign applied by flipping the sign bit; -t (and alpha)
-// multiply the sum once.  External rows are read four at a time.
+// (internal hops from the front, external from the back): each of the eight
+// lanes of a row group loads its own 16 bytes of it and a hop's entry reaches
+// the other lanes by a permute within the group, so the line costs one load
+// instead of eight.  The next row group's line, hop counts (one word) and
+// running output are loaded one step ahead, which leaves the external rows as
+// the only memory round trip of a step.  Internal hops are summed with the
+// sign applied by flipping the sign bit; -t (and alpha) multiply the sum once.
+// External rows are read four at a time.
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__restrict__ x, int64_t ldx,
                                                         T *__restrict__ y, int64_t ldy, double alpha,
@@ -576,26 +579,50 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
         const int sub = lane >> 3, q = lane & 7;
         const int64_t d = d0 + q * EPL;
         const bool dok = d < p.dim_dn, whole = d + EPL <= p.dim_dn;
-        for (int rb = wave * 8; rb < bs; rb += nwave * 8) {
+        const int gbase = lane & ~7;
+        // running output of row r (zero past the last column)
+        auto load_prev = [&](int64_t r) -> vec {
+            const T *yp = y + r * ldy + d;
+            if (whole)
+                return __builtin_nontemporal_load(reinterpret_cast<const vec *>(yp));
+            vec v = (vec)(T)0;
+            if (dok) {
+#pragma unroll
+                for (int e = 0; e < EPL; e++)
+                    v[e] = d + e < p.dim_dn ? yp[e] : (T)0;
+            }
+            return v;
+        };
+        // Lane q of a row group holds slots 4q..4q+3 of the row's line; entry
+        // k reaches every lane of the group by a permute within the group.
+        uint4 Em = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t C = 0;
+        vec prev = (vec)(T)0;
+        int rb = wave * 8;
+        if (rb < bs) {
+            const int64_t r = b0 + min(rb + sub, bs - 1);
+            Em = p.line[r * 8 + q];
+            C = p.cnt[r];
+            if (rb + sub < bs)
+                prev = load_prev(r);
+        }
+        for (; rb < bs; rb += nwave * 8) {
             const int rl = min(rb + sub, bs - 1);
             const bool okr = rb + sub < bs;
             const int64_t r = b0 + rl;
             T *yp = y + r * ldy + d;
-            vec prev = (vec)(T)0;
-            if (okr && dok) {
-                if (whole) {
-                    prev = __builtin_nontemporal_load(reinterpret_cast<const vec *>(yp));
-                } else {
-#pragma unroll
-                    for (int e = 0; e < EPL; e++)
-                        prev[e] = d + e < p.dim_dn ? yp[e] : (T)0;
-                }
+            // the next row group's entries, counts and running output, a step ahead
+            uint4 En = Em;
+            uint32_t Cn = 0;
+            vec prevn = (vec)(T)0;
+            const int rbn = rb + nwave * 8;
+            if (rbn < bs) {
+                const int64_t rn = b0 + min(rbn + sub, bs - 1);
+                En = p.line[rn * 8 + q];
+                Cn = p.cnt[rn];
+                if (rbn + sub < bs)
+                    prevn = load_prev(rn);
             }
-            uint4 E[8];
-#pragma unroll
-            for (int g = 0; g < 8; g++)
-                E[g] = p.line[r * 8 + g];
-            const uint32_t C = p.cnt[r];
             const int ni = (int)(C & 0xffffu), ne = (int)(C >> 16);
             int nim = ni, nem = ne;
             for (int o = 8; o < 64; o <<= 1) {
@@ -604,27 +631,25 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
             }
             nim = __builtin_amdgcn_readfirstlane(nim);
             nem = __builtin_amdgcn_readfirstlane(nem);
-            uint32_t ev[32];
-#pragma unroll
-            for (int g = 0; g < 8; g++) {
-                ev[4 * g] = E[g].x;
-                ev[4 * g + 1] = E[g].y;
-                ev[4 * g + 2] = E[g].z;
-                ev[4 * g + 3] = E[g].w;
-            }
+            auto entry = [&](int k) -> uint32_t {
+                const uint32_t c = (k & 3) == 0 ? Em.x : (k & 3) == 1 ? Em.y : (k & 3) == 2 ? Em.z : Em.w;
+                return (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (k >> 2)) << 2, (int)c);
+            };
             vec acc = (vec)(T)0;
 #pragma unroll
             for (int k0 = 0; k0 < 32; k0 += 8) {
                 if (k0 < nim) {
                     vec v[8];
+                    uint32_t ev[8];
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
-                        const int li = k0 + u < ni ? (int)(ev[k0 + u] & 0x7fffffffu) : bs;
+                        ev[u] = entry(k0 + u);
+                        const int li = k0 + u < ni ? (int)(ev[u] & 0x7fffffffu) : bs;
                         v[u] = xs[li * 8 + q];
                     }
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
-                        const uint32_t sg = ev[k0 + u] & 0x80000000u;
+                        const uint32_t sg = ev[u] & 0x80000000u;
 #pragma unroll
                         for (int c = 0; c < EPL; c++)
                             acc[c] += flip_sign(v[u][c], sg);
@@ -635,16 +660,18 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
             for (int k0 = 0; k0 < 32; k0 += XB) {
                 if (k0 < nem) {
                     vec v[XB];
+                    uint32_t ev[XB];
 #pragma unroll
                     for (int u = 0; u < XB; u++) {
                         const bool live = k0 + u < ne;
-                        const int64_t row = live ? (int64_t)(ev[31 - (k0 + u)] & 0x7fffffffu) : r;
+                        ev[u] = entry(31 - (k0 + u));
+                        const int64_t row = live ? (int64_t)(ev[u] & 0x7fffffffu) : r;
                         v[u] = load_row(x + row * ldx, d);
                     }
 #pragma unroll
                     for (int u = 0; u < XB; u++) {
                         const bool live = k0 + u < ne;
-                        const uint32_t sg = ev[31 - (k0 + u)] & 0x80000000u;
+                        const uint32_t sg = ev[u] & 0x80000000u;
 #pragma unroll
                         for (int c = 0; c < EPL; c++)
                             acc[c] += live ? flip_sign(v[u][c], sg) : (T)0;
@@ -680,6 +707,9 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                     }
                 }
             }
+            Em = En;
+            C = Cn;
+            prev = prevn;
         }
     }
     if (MODE != HV_STORE) {
