@@ -68,6 +68,14 @@ __device__ inline double block_sum2(double v, double *scratch)
     return s;
 }
 
+// wave64 shuffle tree; the sum lands in lane 0
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
 __device__ inline float flip_sign(float v, uint32_t sg) { return __int_as_float(__float_as_int(v) ^ (int)sg); }
 __device__ inline double flip_sign(double v, uint32_t sg)
 {
@@ -541,7 +549,6 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
             v[e] = d + e < p.dim_dn ? row[d + e] : (T)0;
         return v;
     };
-    __shared__ double red[16];
     if (MODE == HV_LANCZOS)
         alpha = coef[0];
     else if (MODE == HV_FUSED)
@@ -713,18 +720,30 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
         }
     }
     if (MODE != HV_STORE) {
-        const double s0 = block_sum2(acc0, red);
-        if (threadIdx.x == 0)
-            partials[blockIdx.x] = s0;
-        if (MODE == HV_RESIDUAL || MODE == HV_FUSED) {
-            const double s1 = block_sum2(acc1, red);
-            if (threadIdx.x == 0)
-                partials[gridDim.x + blockIdx.x] = s1;
+        // all partial sums of the workgroup in one round: wave sums, one
+        // barrier, then lane 0 of wave 0 adds the waves in a fixed order
+        __shared__ double red[3][16];
+        const double s0 = wave_sum(acc0);
+        const double s1 = (MODE == HV_RESIDUAL || MODE == HV_FUSED) ? wave_sum(acc1) : 0.0;
+        const double s2 = MODE == HV_FUSED ? wave_sum(acc2) : 0.0;
+        if (lane == 0) {
+            red[0][wave] = s0;
+            red[1][wave] = s1;
+            red[2][wave] = s2;
         }
-        if (MODE == HV_FUSED) {
-            const double s2 = block_sum2(acc2, red);
-            if (threadIdx.x == 0)
-                partials[2 * gridDim.x + blockIdx.x] = s2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+            for (int w = 0; w < nwave; w++) {
+                t0 += red[0][w];
+                t1 += red[1][w];
+                t2 += red[2][w];
+            }
+            partials[blockIdx.x] = t0;
+            if (MODE == HV_RESIDUAL || MODE == HV_FUSED)
+                partials[gridDim.x + blockIdx.x] = t1;
+            if (MODE == HV_FUSED)
+                partials[2 * gridDim.x + blockIdx.x] = t2;
         }
     }
 }
