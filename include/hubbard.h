@@ -130,8 +130,10 @@ int hubbard_set_precision(hubbard_h h, int precision);
 /* Seed of the start vector used by hubbard_lanczos (default 12043425). */
 int hubbard_set_seed(hubbard_h h, uint64_t seed);
 
-/* y = H x (Sec. 4.3: H_up (x) I, I (x) H_dn and the interaction term in one
- * kernel).  x, y: device arrays of dim elements in J order, double under
+/* y = H x (Sec. 4.3: H_up (x) I, I (x) H_dn and the interaction term; two
+ * passes over the rows of the dim_up x dim_dn view, the down-spin hops and the
+ * interaction from rows staged in LDS, then the up-spin hops as row
+ * combinations).  x, y: device arrays of dim elements in J order, double under
  * HUBBARD_FP64 and float under HUBBARD_MIXED; y is overwritten and must not
  * overlap x.  Asynchronous on the handle's stream. */
 int hubbard_apply(hubbard_h h, const void *x, void *y);
@@ -140,8 +142,10 @@ int hubbard_apply(hubbard_h h, const void *x, void *y);
  * elements at row strides ldx and ldy (elements, >= dim_dn; the subvectors of
  * Sec. 4.3, Fig. slots).  Padding elements are neither read nor written.
  * hubbard_info gives the stride the library uses for its own vectors
- * (ld_pref): rows that start on 256-byte boundaries let the up-spin pass keep
- * whole cache lines per slab. */
+ * (ld_pref, a multiple of 64 elements): strides that are a multiple of 128
+ * bytes (and buffers aligned to 128 bytes) select the blocked up-spin pass,
+ * which works on one cache line of every row at a time; other strides take a
+ * slower pass. */
 int hubbard_apply_ld(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t ldy);
 
 /* Lanczos ground state (Sec. 2.2, Alg. 1, two-vector form): iterates until
