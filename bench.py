@@ -350,11 +350,11 @@ def stored_traffic(dim):
 # ------------------------------------------------------------------ summaries
 
 def _kernel_family(name):
-    for fam in ("hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel",
+    for fam in ("batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "batch_init_state_kernel",
+                "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel",
                 "axpy_norm_kernel",
                 "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
-                "psi_acc_kernel", "batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "copyBuffer",
-                "elementwise"):
+                "psi_acc_kernel", "copyBuffer", "elementwise"):
         if fam in name:
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""

@@ -14,6 +14,7 @@ struct BatchState {
     double S[8];     // {1/s of the current vector, alpha, beta, c, -, -, a_j, b_{j+1}}
     double scale;    // running max_k |a_k| + b_k (breakdown test)
     double e_prev;   // Ritz value of the previous step
+    double e_prev2;  // and of the step before
     int32_t j;       // steps done
     int32_t stopped; // set by the step that stops the instance
     int32_t cur;     // 0: vec0 holds s f_j, 1: vec1 does

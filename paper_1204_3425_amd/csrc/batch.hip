@@ -163,6 +163,16 @@ __global__ __launch_bounds__(kThreads) void batch_axpy_kernel(const BatchInst *_
 // Number of negative pivots of the LDL^T factorisation of T_m - x I (T_m:
 // diagonal hist[0], hist[2], ..., off-diagonal hist[1], hist[3], ...), which
 // by Sylvester's law of inertia is the number of eigenvalues of T_m below x.
+// The pivot recurrence is a serial chain, so the division is the hardware
+// reciprocal estimate refined by one Newton step (r' = r + r (1 - p r), which
+// squares its relative error to below FP64 rounding) times the squared
+// off-diagonal, instead of the longer correctly rounded division sequence.
+__device__ inline double recip(double p)
+{
+    const double r = __builtin_amdgcn_rcp(p);
+    return fma(r, fma(-p, r, 1.0), r);
+}
+
 __device__ int negative_pivots(const double *__restrict__ hist, int m, double x)
 {
     const double floor_piv = 1e-290;
@@ -172,7 +182,7 @@ __device__ int negative_pivots(const double *__restrict__ hist, int m, double x)
     int neg = piv < 0.0;
     for (int i = 1; i < m; i++) {
         const double e = hist[2 * i - 1];
-        piv = (hist[2 * i] - x) - e * (e / piv);
+        piv = (hist[2 * i] - x) - (e * e) * recip(piv);
         if (fabs(piv) < floor_piv)
             piv = -floor_piv;
         neg += piv < 0.0;
@@ -185,21 +195,43 @@ __device__ int negative_pivots(const double *__restrict__ hist, int m, double x)
 // [lo, hi] (no eigenvalue below lo, at least one below hi), and the bracket
 // shrinks to the two points around the first count above zero, until no point
 // falls strictly inside it.  Returns hi, as the host's bisection does.
-__device__ double lowest_eigenvalue(const double *__restrict__ hist, int m, double *sh, int *first)
+// The bracket starts just below the previous step's value e_prev (by Cauchy
+// interlacing the lowest eigenvalue of T_m is at most that of T_{m-1}), width
+// four times the last change, when two counts confirm it; otherwise it is
+// the Gershgorin interval.  Either start ends at the same pair of points.
+__device__ double lowest_eigenvalue(const double *__restrict__ hist, int m, double e_prev, double e_prev2,
+                                    double *sh, int *first)
 {
-    if (threadIdx.x == 0) {
-        double lo = hist[0], hi = hist[0];
-        for (int i = 0; i < m; i++) {
-            const double rad = (i > 0 ? fabs(hist[2 * i - 1]) : 0.0) + (i < m - 1 ? fabs(hist[2 * i + 1]) : 0.0);
-            lo = fmin(lo, hist[2 * i] - rad);
-            hi = fmax(hi, hist[2 * i] + rad);
+    const int nt = (int)blockDim.x;
+    if (threadIdx.x < 2) {
+        sh[4 + threadIdx.x] = 0.0;
+        if (m >= 3) {
+            const double scale = fmax(1.0, fabs(e_prev));
+            const double width = fmax(4.0 * fabs(e_prev - e_prev2), 1e-12 * scale);
+            const double hi = e_prev + 4.0 * 0x1p-52 * scale;
+            const double lo = e_prev - width;
+            const int c = negative_pivots(hist, m, threadIdx.x == 0 ? lo : hi);
+            sh[4 + threadIdx.x] = threadIdx.x == 0 ? (c == 0 ? lo : NAN) : (c > 0 ? hi : NAN);
         }
-        const double pad = 0x1p-52 * (fabs(lo) + fabs(hi)) + 1e-290;
-        sh[0] = lo - pad;
-        sh[1] = hi + pad;
     }
     __syncthreads();
-    const int nt = (int)blockDim.x;
+    if (threadIdx.x == 0) {
+        if (m >= 3 && !isnan(sh[4]) && !isnan(sh[5])) {
+            sh[0] = sh[4];
+            sh[1] = sh[5];
+        } else {
+            double lo = hist[0], hi = hist[0];
+            for (int i = 0; i < m; i++) {
+                const double rad = (i > 0 ? fabs(hist[2 * i - 1]) : 0.0) + (i < m - 1 ? fabs(hist[2 * i + 1]) : 0.0);
+                lo = fmin(lo, hist[2 * i] - rad);
+                hi = fmax(hi, hist[2 * i] + rad);
+            }
+            const double pad = 0x1p-52 * (fabs(lo) + fabs(hi)) + 1e-290;
+            sh[0] = lo - pad;
+            sh[1] = hi + pad;
+        }
+    }
+    __syncthreads();
     for (int round = 0; round < 64; round++) {
         const double lo = sh[0], hi = sh[1];
         auto point = [&](int t) { return fmin(hi, fmax(lo, lo + (hi - lo) * ((double)(t + 1) / (double)(nt + 1)))); };
@@ -233,11 +265,12 @@ __device__ double lowest_eigenvalue(const double *__restrict__ hist, int m, doub
 // energy, breakdown, exhausted-space and iteration-count tests in the
 // single-instance driver's order, and the step's mailbox entry; the two
 // vectors swap roles (the updated q holds b_{j+1} f_{j+1}).
-__global__ __launch_bounds__(kThreads) void batch_reduce_kernel(const BatchInst *__restrict__ insts, int mode,
-                                                                double *__restrict__ mailbox)
+template <int NT>
+__global__ __launch_bounds__(NT) void batch_reduce_kernel(const BatchInst *__restrict__ insts, int mode,
+                                                         double *__restrict__ mailbox)
 {
-    __shared__ double red[kThreads / 64];
-    __shared__ double sh[4];
+    __shared__ double red[NT / 64];
+    __shared__ double sh[6];
     __shared__ int first;
     const BatchInst &in = insts[blockIdx.x];
     BatchState *st = in.st;
@@ -274,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void batch_reduce_kernel(const BatchInst 
     if (!isfinite(a) || !isfinite(b)) {
         code = kMailBad;
     } else {
-        e = lowest_eigenvalue(in.hist, m, sh, &first);
+        e = lowest_eigenvalue(in.hist, m, st->e_prev, st->e_prev2, sh, &first);
     }
     if (threadIdx.x == 0) {
         if (code == kMailRunning) {
@@ -290,6 +323,7 @@ __global__ __launch_bounds__(kThreads) void batch_reduce_kernel(const BatchInst 
                     code = HUBBARD_STOP_MAXITER;
             }
         }
+        st->e_prev2 = st->e_prev;
         st->e_prev = e;
         st->j = m;
         S[2] = -b * S[0];
@@ -315,6 +349,7 @@ __global__ void batch_init_state_kernel(BatchState *st)
         st->S[1] = 1.0;
         st->scale = 0.0;
         st->e_prev = 0.0;
+        st->e_prev2 = 0.0;
         st->j = 0;
         st->stopped = 0;
         st->cur = 0;
@@ -333,11 +368,12 @@ void launch_batch_step(BatchInst *insts_dev, int n_inst, const BatchItem *items_
         HUB_HIP(hipFuncSetAttribute((const void *)hv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     hipLaunchKernelGGL(hv, dim3(n_items), dim3(kThreads), lds_bytes, s, insts_dev, items_dev);
     HUB_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(n_inst), dim3(kThreads), 0, s, insts_dev, 0, mailbox_dev);
+    hipLaunchKernelGGL(batch_reduce_kernel<kThreads>, dim3(n_inst), dim3(kThreads), 0, s, insts_dev, 0, mailbox_dev);
     HUB_HIP(hipGetLastError());
     hipLaunchKernelGGL(batch_axpy_kernel<T>, dim3(n_items), dim3(kThreads), 0, s, insts_dev, items_dev);
     HUB_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(n_inst), dim3(kThreads), 0, s, insts_dev, 1, mailbox_dev);
+    // the step's last reduction also runs the multisection: more points, fewer rounds
+    hipLaunchKernelGGL(batch_reduce_kernel<1024>, dim3(n_inst), dim3(1024), 0, s, insts_dev, 1, mailbox_dev);
     HUB_HIP(hipGetLastError());
 }
 
