@@ -43,7 +43,7 @@ struct Pinned {
     Pinned &operator=(const Pinned &) = delete;
 };
 
-constexpr int64_t kItemElems = 8192;  // target elements per work item
+constexpr int64_t kItemElems = 2048;  // target elements per work item
 
 int64_t rows_per_item(const hubbard *h)
 {

@@ -190,33 +190,62 @@ __device__ int negative_pivots(const double *__restrict__ hist, int m, double x)
     return neg;
 }
 
-// Lowest eigenvalue of T_m by multisection: every thread of the workgroup
-// counts the eigenvalues below one of blockDim.x points of the bracket
-// [lo, hi] (no eigenvalue below lo, at least one below hi), and the bracket
-// shrinks to the two points around the first count above zero, until no point
-// falls strictly inside it.  Returns hi, as the host's bisection does.
-// The bracket starts just below the previous step's value e_prev (by Cauchy
-// interlacing the lowest eigenvalue of T_m is at most that of T_{m-1}), width
-// four times the last change, when two counts confirm it; otherwise it is
-// the Gershgorin interval.  Either start ends at the same pair of points.
+// The same count at P points in one pass: the P pivot chains are independent,
+// so they hide each other's latency.
+template <int P>
+__device__ void negative_pivots_p(const double *__restrict__ hist, int m, const double *x, int *neg)
+{
+    const double floor_piv = 1e-290;
+    double piv[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        piv[k] = hist[0] - x[k];
+        if (fabs(piv[k]) < floor_piv)
+            piv[k] = -floor_piv;
+        neg[k] = piv[k] < 0.0;
+    }
+    for (int i = 1; i < m; i++) {
+        const double e = hist[2 * i - 1], d = hist[2 * i];
+        const double e2 = e * e;
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            piv[k] = (d - x[k]) - e2 * recip(piv[k]);
+            if (fabs(piv[k]) < floor_piv)
+                piv[k] = -floor_piv;
+            neg[k] += piv[k] < 0.0;
+        }
+    }
+}
+
+// Lowest eigenvalue of T_m by multisection: the workgroup counts the
+// eigenvalues below 2 * blockDim.x points of the bracket [lo, hi] (no
+// eigenvalue below lo, at least one below hi), and the bracket shrinks to the
+// two points around the first count above zero, until no double lies strictly
+// inside it.  Returns hi, as the host's bisection does.  The bracket starts
+// just below the previous step's value e_prev (by Cauchy interlacing the
+// lowest eigenvalue of T_m is at most that of T_{m-1}), four times the last
+// change wide, when two counts confirm it; otherwise it is the Gershgorin
+// interval.  Either start ends at the same pair of doubles.
 __device__ double lowest_eigenvalue(const double *__restrict__ hist, int m, double e_prev, double e_prev2,
                                     double *sh, int *first)
 {
-    const int nt = (int)blockDim.x;
+    constexpr int P = 2;
+    const int np = (int)blockDim.x * P;
     if (threadIdx.x < 2) {
-        sh[4 + threadIdx.x] = 0.0;
+        sh[4 + threadIdx.x] = NAN;
         if (m >= 3) {
             const double scale = fmax(1.0, fabs(e_prev));
             const double width = fmax(4.0 * fabs(e_prev - e_prev2), 1e-12 * scale);
             const double hi = e_prev + 4.0 * 0x1p-52 * scale;
             const double lo = e_prev - width;
             const int c = negative_pivots(hist, m, threadIdx.x == 0 ? lo : hi);
-            sh[4 + threadIdx.x] = threadIdx.x == 0 ? (c == 0 ? lo : NAN) : (c > 0 ? hi : NAN);
+            if (threadIdx.x == 0 ? c == 0 : c > 0)
+                sh[4 + threadIdx.x] = threadIdx.x == 0 ? lo : hi;
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (m >= 3 && !isnan(sh[4]) && !isnan(sh[5])) {
+        if (!isnan(sh[4]) && !isnan(sh[5])) {
             sh[0] = sh[4];
             sh[1] = sh[5];
         } else {
@@ -230,31 +259,39 @@ __device__ double lowest_eigenvalue(const double *__restrict__ hist, int m, doub
             sh[0] = lo - pad;
             sh[1] = hi + pad;
         }
+        sh[2] = nextafter(sh[0], INFINITY) < sh[1] ? 0.0 : 1.0;
     }
     __syncthreads();
-    for (int round = 0; round < 64; round++) {
+    for (int round = 0; round < 64 && sh[2] == 0.0; round++) {
         const double lo = sh[0], hi = sh[1];
-        auto point = [&](int t) { return fmin(hi, fmax(lo, lo + (hi - lo) * ((double)(t + 1) / (double)(nt + 1)))); };
-        const double x = point((int)threadIdx.x);
-        const int c = negative_pivots(hist, m, x);
+        auto point = [&](int t) { return fmin(hi, fmax(lo, lo + (hi - lo) * ((double)(t + 1) / (double)(np + 1)))); };
+        double x[P];
+        int c[P];
+#pragma unroll
+        for (int k = 0; k < P; k++)
+            x[k] = point((int)threadIdx.x * P + k);
+        negative_pivots_p<P>(hist, m, x, c);
         if (threadIdx.x == 0)
-            *first = nt;
+            *first = np;
         __syncthreads();
-        if (c > 0)
-            atomicMin(first, (int)threadIdx.x);
-        __syncthreads();
-        const int f = *first;
+        int mine = np;
+#pragma unroll
+        for (int k = P - 1; k >= 0; k--)
+            if (c[k] > 0)
+                mine = (int)threadIdx.x * P + k;
+        if (mine < np)
+            atomicMin(first, mine);
         __syncthreads();
         if (threadIdx.x == 0) {
+            const int f = *first;
             const double nlo = f == 0 ? lo : point(f - 1);
-            const double nhi = f == nt ? hi : point(f);
-            sh[2] = (nlo == lo && nhi == hi) ? 1.0 : 0.0;
+            const double nhi = f == np ? hi : point(f);
+            // done when a round changed nothing or no double is left strictly inside
+            sh[2] = ((nlo == lo && nhi == hi) || !(nextafter(nlo, INFINITY) < nhi)) ? 1.0 : 0.0;
             sh[0] = nlo;
             sh[1] = nhi;
         }
         __syncthreads();
-        if (sh[2] != 0.0)
-            break;
     }
     return sh[1];
 }
@@ -372,8 +409,7 @@ void launch_batch_step(BatchInst *insts_dev, int n_inst, const BatchItem *items_
     HUB_HIP(hipGetLastError());
     hipLaunchKernelGGL(batch_axpy_kernel<T>, dim3(n_items), dim3(kThreads), 0, s, insts_dev, items_dev);
     HUB_HIP(hipGetLastError());
-    // the step's last reduction also runs the multisection: more points, fewer rounds
-    hipLaunchKernelGGL(batch_reduce_kernel<1024>, dim3(n_inst), dim3(1024), 0, s, insts_dev, 1, mailbox_dev);
+    hipLaunchKernelGGL(batch_reduce_kernel<kThreads>, dim3(n_inst), dim3(kThreads), 0, s, insts_dev, 1, mailbox_dev);
     HUB_HIP(hipGetLastError());
 }
 
