@@ -5,7 +5,9 @@ CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
 with the GPU library (``paper_1204_3425_amd``) and never imports it.
 
 The arithmetic lives in ``hubbard_oracle.c`` (plain C, built with gcc -O2, one
-thread); this module only marshals arguments.  Every function cites the part
+thread); this module only marshals arguments, except ``Model.lowest_states``,
+which hands the dense H built from that C code to numpy's symmetric
+eigen-solver.  Every function cites the part
 of Siro & Harju (arXiv:1204.3425) it follows.
 """
 from __future__ import annotations
@@ -197,6 +199,17 @@ class Model:
             H[:, c] = self.apply(e)
             e[c] = 0.0
         return H
+
+    def lowest_states(self, k: int):
+        """The k lowest eigenvalues of the sector Hamiltonian, repeated by
+        multiplicity, and an orthonormal set of eigenvectors for them, one per
+        row (Sec. 2.2 names the ground state and the lowest excited states as
+        the wanted output of the method).  This is the definition written out:
+        the full symmetric eigenproblem of the dense H (LAPACK through
+        numpy.linalg.eigh), so small sectors only."""
+        assert 1 <= k <= self.dim
+        w, v = np.linalg.eigh(self.dense())
+        return w[:k].copy(), np.ascontiguousarray(v[:, :k].T)
 
     def lanczos(self, f1: np.ndarray, tol: float = 1e-12, max_iter: int = 300, want_psi: bool = False):
         """Alg. 1 from the unit start vector f1; returns a dict with a_j, b_{j+1},

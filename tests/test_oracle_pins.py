@@ -304,3 +304,87 @@ def test_breakdown_on_one_dimensional_sector():
     r = m.lanczos(np.ones(1), tol=1e-12, max_iter=10, want_psi=True)
     assert r["n_iter"] == 1 and r["converged"] == 2
     assert abs(r["E0"]) < 1e-300 and r["residual"] < 1e-300
+
+
+# ------------------------------------------------------------------ lowest states (Sec. 2.2)
+
+def _check_eigvecs(m, w, V):
+    """Rows of V are orthonormal and H v = w v for each."""
+    assert np.abs(V @ V.T - np.eye(len(w))).max() < 1e-12
+    for e, v in zip(w, V):
+        assert np.linalg.norm(m.apply(v) - e * v) < 1e-11 * max(1.0, abs(e))
+
+
+@pytest.mark.parametrize("U", [0.0, 3.7])
+@pytest.mark.parametrize("t", [1.3, -0.6])
+def test_lowest_states_dimer_full_spectrum(U, t):
+    """Two sites, one electron of each spin: the four levels are the triplet 0,
+    the antisymmetric doubly-occupied state U, and (U -+ sqrt(U^2 + 16 t^2)) / 2."""
+    m = oracle.Model(2, [(0, 1)], 1, 1, t, U)
+    w, V = m.lowest_states(4)
+    r = math.sqrt(U * U + 16 * t * t)
+    want = np.sort([0.0, U, (U - r) / 2, (U + r) / 2])
+    assert np.allclose(w, want, rtol=0, atol=1e-13)
+    _check_eigvecs(m, w, V)
+
+
+def _atomic_spectrum(ns, nu, nd, U):
+    """t = 0: level U d with multiplicity C(Ns, d) C(Ns-d, Nu-d) C(Ns-Nu, Nd-d)
+    (choose the doubly occupied sites, then the lone up spins, then the lone
+    down spins among the sites without an up spin)."""
+    out = []
+    for d in range(0, min(nu, nd) + 1):
+        mult = math.comb(ns, d) * math.comb(ns - d, nu - d) * math.comb(ns - nu, nd - d)
+        out += [U * d] * mult
+    return np.sort(np.array(out, dtype=float))
+
+
+@pytest.mark.parametrize("ns,nu,nd", [(4, 3, 3), (5, 3, 2), (6, 3, 3)])
+def test_lowest_states_atomic_limit_multiplicities(ns, nu, nd):
+    U = 2.5
+    m = oracle.Model(ns, workload.ring(ns), nu, nd, 0.0, U)
+    ref = _atomic_spectrum(ns, nu, nd, U)
+    assert len(ref) == m.dim
+    w, V = m.lowest_states(m.dim)
+    assert np.array_equal(w.round(12), ref.round(12))
+    _check_eigvecs(m, w, V)
+
+
+def _free_spectrum(levels, nu, nd):
+    """U = 0: every eigenvalue is a sum over N_up distinct levels plus a sum over
+    N_dn distinct levels (Slater determinants of each spin)."""
+    import itertools
+    su = [sum(c) for c in itertools.combinations(levels, nu)]
+    sd = [sum(c) for c in itertools.combinations(levels, nd)]
+    return np.sort(np.add.outer(su, sd).ravel())
+
+
+@pytest.mark.parametrize("kind,ns,nu,nd", [("ring", 6, 2, 3), ("ring", 7, 3, 3), ("chain", 6, 3, 2)])
+def test_lowest_states_free_fermion_spectrum(kind, ns, nu, nd):
+    """U = 0: ring levels -2t cos(2 pi k / Ns); open-chain levels -2t cos(pi k / (Ns+1))."""
+    t = 0.8
+    if kind == "ring":
+        edges = workload.ring(ns)
+        lev = [-2 * t * math.cos(2 * math.pi * k / ns) for k in range(ns)]
+    else:
+        edges = workload.chain(ns)
+        lev = [-2 * t * math.cos(math.pi * k / (ns + 1)) for k in range(1, ns + 1)]
+    m = oracle.Model(ns, edges, nu, nd, t, 0.0)
+    ref = _free_spectrum(lev, nu, nd)
+    k = min(40, m.dim)
+    w, V = m.lowest_states(k)
+    assert np.allclose(w, ref[:k], rtol=0, atol=1e-11)
+    _check_eigvecs(m, w, V)
+
+
+def test_lowest_states_trace_and_ordering():
+    """Interacting case: the full spectrum is ascending and sums to the trace,
+    U times the number of doubly occupied sites summed over the basis,
+    sum_d d * mult(d) with the multiplicities of the atomic limit."""
+    ns, nu, nd, U = 6, 3, 2, 4.0
+    m = oracle.Model(ns, workload.torus(2, 3), nu, nd, 1.0, U)
+    w, V = m.lowest_states(m.dim)
+    assert np.all(np.diff(w) >= 0)
+    ref = _atomic_spectrum(ns, nu, nd, U).sum()
+    assert w.sum() == pytest.approx(ref, rel=1e-12)
+    _check_eigvecs(m, w, V)
