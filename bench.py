@@ -16,6 +16,7 @@ Printed JSON line (one):
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counts when they were taken
                  on the current kernel sources, else null
   cpu_baseline   the sequential FP64 oracle on one host core, bounded sample
+  excited        the k lowest states of the same sector (hubbard_lowest_states)
 
 Other modes:
   --calibrate-copy           also run one device copy of known size (for counter scaling)
@@ -196,6 +197,65 @@ def bench_serving(hb, torch, count, seed_rate=None):
             "service_p99_s": round(float(np.percentile(svc, 99)), 4),
             "lanczos_steps": int(dims), "peak_reserved_gb": round(st["peak_reserved"] / 1e9, 2),
             "budget_gb": round(st["budget"] / 1e9, 1), "max_active_batch": st["max_active_batch"]}
+
+
+EXCITED_TOL = {"square4x4": 1e-12, "ring8": 1e-14}
+
+
+def bench_excited(hb, torch, p, k, tol):
+    """The k lowest states of one sector through hubbard_lowest_states (FP64,
+    eigenvectors kept): state 0 is the plain ground-state solve, state i >= 1
+    a Lanczos run that projects out the i lower vectors at every step.  The
+    vectors are copied to the host for the oracle's check in the CPU-baseline
+    leg (bench_excited.vectors)."""
+    h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    psi = torch.zeros((k, p.dim), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, res = hb.hubbard_lowest_states(h, k, tol=tol, max_iter=600, precision=hb.HUBBARD_FP64, seed=p.seed,
+                                      psi=psi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    G = (psi @ psi.T).cpu()
+    ortho = float((G - torch.eye(k, dtype=G.dtype)).abs().max())
+    bench_excited.vectors[p.name] = (p, E, psi.cpu().numpy(), [r["residual"] for r in res])
+    del psi
+    return {"workload": p.name, "dim": p.dim, "k": k, "tol": tol, "seconds": round(dt, 3),
+            "E": [float(e) for e in E], "gap_E1_minus_E0": float(E[1] - E[0]) if k > 1 else None,
+            "iters": [r["n_iter"] for r in res], "stop": [r["stop"] for r in res],
+            "ms_per_iter_first_pass": [round(r["seconds_per_iter"] * 1e3, 4) for r in res],
+            "residual": [float("%.3g" % r["residual"]) for r in res], "max_ortho_err": float("%.3g" % ortho)}
+
+
+bench_excited.vectors = {}
+
+
+def oracle_excited_check():
+    """The oracle beside the excited-state leg: for the 8-site ring its dense
+    eigenproblem (timed) against the GPU energies; for the 4x4 lattice, whose
+    spectrum the oracle cannot reach, (H psi_i)[J] from the oracle on 64
+    sampled rows against E_i psi_i[J], within the residual the GPU reports."""
+    import numpy as np
+    import oracle
+    out = {}
+    for name, (p, E, Psi, resid) in bench_excited.vectors.items():
+        m = oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+        k = len(E)
+        if p.dim <= 6000:
+            t0 = time.perf_counter()
+            w = m.lowest_states(k)[0]
+            dt = time.perf_counter() - t0
+            err = float(np.max(np.abs(E - w) / np.maximum(1.0, np.abs(w))))
+            out[name] = {"oracle_seconds": round(dt, 3), "E_max_rel_err_vs_oracle": float("%.3g" % err)}
+        else:
+            rows = np.random.default_rng(p.seed).choice(p.dim, 64, replace=False)
+            worst = 0.0
+            for i in range(k):
+                hv = m.apply_rows(Psi[i], rows)
+                worst = max(worst, float(np.max(np.abs(hv - E[i] * Psi[i][rows]))) / max(resid[i], 1e-300))
+            out[name] = {"sampled_rows": 64, "max_row_error_over_residual": float("%.3g" % worst)}
+        del m
+    return out
 
 
 def golden(name):
@@ -449,6 +509,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="solves in the batch leg (0 skips it)")
     ap.add_argument("--serve", type=int, default=200, help="requests in the serving leg (0 skips it)")
     ap.add_argument("--no-small", action="store_true", help="skip the 14-site and 8-site ring legs")
+    ap.add_argument("--excited", type=int, default=3,
+                    help="lowest states in the excited-state leg on the 4x4 lattice (0 skips it)")
     ap.add_argument("--summarize-trace")
     ap.add_argument("--summarize-pmc", nargs=2)
     args = ap.parse_args()
@@ -532,6 +594,14 @@ def main():
         out["ring14"] = bench_ring14(hb, torch, 51)
         log("ring8 leg")
         out["ring8"] = bench_ring8(hb, torch)
+    if args.excited:
+        log("excited-state leg:", args.excited, "lowest states of", p.name)
+        ex = {"square4x4": bench_excited(hb, torch, p, args.excited, EXCITED_TOL["square4x4"])}
+        if not args.no_small:
+            log("excited-state leg: 6 lowest states of the 8-site ring")
+            ex["ring8"] = bench_excited(hb, torch, workload.problem("ring8_3u3d_U4", 8, workload.ring(8), 3, 3,
+                                                                    1.0, 4.0), 6, EXCITED_TOL["ring8"])
+        out["excited"] = ex
     batch_probs = None
     if args.batch:
         log("batch leg:", args.batch, "solves")
@@ -551,6 +621,10 @@ def main():
             cs = oracle_serving_check(bench_serving.results)
             if cs is not None:
                 cb["serving"] = cs
+        if bench_excited.vectors:
+            log("oracle beside the excited-state leg")
+            cb["excited"] = oracle_excited_check()
+            bench_excited.vectors.clear()
         if batch_probs is not None:
             log("oracle on the batch-leg solves")
             ob = oracle_batch_check(batch_probs, out["batch"])

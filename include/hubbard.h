@@ -159,6 +159,39 @@ int hubbard_lanczos(hubbard_h h, double tol, int max_iter, double *E0, double *p
 /* As hubbard_lanczos with every option and the full result record. */
 int hubbard_lanczos_ex(hubbard_h h, const hubbard_opts *opts, hubbard_result *res);
 
+/* The k lowest eigenvalues of the sector, repeated by multiplicity, and their
+ * eigenvectors (Sec. 2.2: the ground state and the lowest excited states),
+ * found one after another: state i is the ground state of P H P with
+ * P = 1 - sum_{l<i} psi_l psi_l^T, run as Alg. 1 with every new Lanczos vector
+ * projected through P (the start vector too), followed by the replayed pass
+ * that accumulates psi_i; psi_i is projected once more, normalised and signed
+ * so that <psi_i, f1^(i)> > 0.  State i starts from its own vector f1^(i): the
+ * seeded vector of hubbard_start_raw with seed opts->seed + i (state 0 from
+ * opts->start when that is given).  Separate starts are what lets a degenerate
+ * level come out once per eigenvector (in no particular order within the
+ * level): one start vector shared by all states would have, inside the level,
+ * only the component that the level's first state takes away.
+ *   k: 1..16, at most dim.
+ *   opts: tol, max_iter and precision as for hubbard_lanczos_ex, applied to
+ *     every state (the energy test of Sec. 2.2 per state); seed and start as
+ *     above; opts->psi and the history arrays must be NULL.
+ *   E: host array[k] receiving E_0 <= E_1 <= ... (lowest Ritz value of each
+ *     deflated run; ties and near-ties may come out in either order).
+ *   psi: NULL, or a device FP64 array of k * dim elements receiving psi_i at
+ *     psi + i * dim (J order).  With NULL the library allocates k * dim
+ *     doubles for the duration of the call.
+ *   res: NULL, or a host array[k] of results; res[i].residual is the FP64
+ *     |H psi_i - E_i psi_i| of the full H (not of P H P).
+ * The error of E_i is of the order of tol plus the squared eigenvector errors
+ * of the lower states, so ask for tol well below the accuracy wanted for the
+ * upper states.  A deflated step costs one H.v and two passes over the i lower
+ * vectors; the large-sector fused step is used for state 0 only.
+ * Errors: EINVAL (bad k or opts, or a start vector inside the span of the lower
+ * states), ENOMEM, EDEVICE.  Synchronous.  Returns the most severe per-state
+ * status (OK or ENOCONV). */
+int hubbard_lowest_states(hubbard_h h, int k, const hubbard_opts *opts, double *E, double *psi,
+                          hubbard_result *res);
+
 /* Sizes of the handle's sector and tables. */
 int hubbard_info(hubbard_h h, hubbard_info_t *info);
 

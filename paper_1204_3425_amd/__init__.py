@@ -115,6 +115,7 @@ def _load():
         "hubbard_export_table": [vp, i32, vp, vp],
         "hubbard_start_raw": [u64, i64, vp, vp],
         "hubbard_lanczos_batch": [vp, i32, ctypes.POINTER(hubbard_opts), ctypes.POINTER(hubbard_result)],
+        "hubbard_lowest_states": [vp, i32, ctypes.POINTER(hubbard_opts), vp, vp, ctypes.POINTER(hubbard_result)],
         "hubbard_server_create": [ctypes.c_size_t, i32, ctypes.POINTER(vp)],
         "hubbard_server_submit": [vp, ctypes.POINTER(hubbard_request), ctypes.POINTER(ctypes.c_uint64)],
         "hubbard_server_poll": [vp, ctypes.POINTER(hubbard_completion), i32, ctypes.POINTER(ctypes.c_int), i32],
@@ -326,6 +327,23 @@ def hubbard_lanczos_batch(handles, tol=1e-12, max_iter=300, precision=None, seed
     if rc < 0:
         raise HubbardError(rc, "hubbard_lanczos_batch", hubbard_last_error())
     return [_result_dict(res[i], hists[i]) for i in range(n)]
+
+
+def hubbard_lowest_states(h: Handle, k: int, tol=1e-12, max_iter=300, precision=None, seed=None, start=None,
+                          psi=None, stream="current"):
+    """The k lowest eigenvalues (with multiplicity) and, when psi is given (a
+    contiguous device FP64 tensor of k * dim elements, e.g. shape (k, dim)),
+    their eigenvectors; returns (E, results) with E a numpy array of k values
+    and results one dict per state as hubbard_lanczos_ex returns."""
+    if stream == "current":
+        hubbard_set_stream(h, _current_stream())
+    o = _opts(h, tol, max_iter, precision, seed, start, None, None)
+    E = np.zeros(max(int(k), 1))
+    res = (hubbard_result * max(int(k), 1))()
+    pp = _dev_ptr(psi, "float64", int(k) * h.dim, "psi") if psi is not None else None
+    _check(_lib.hubbard_lowest_states(h, int(k), ctypes.byref(o), E.ctypes.data, pp, res),
+           "hubbard_lowest_states", allow=(HUBBARD_OK, HUBBARD_ENOCONV))
+    return E[:k].copy(), [_result_dict(res[i], None) for i in range(int(k))]
 
 
 def hubbard_info(h: Handle) -> dict:

@@ -324,8 +324,15 @@ struct LanczosOut {
 // sectors from this size on take the fused Lanczos step
 constexpr int64_t kFusedMinDim = 1 << 16;
 
+// Lower eigenvectors to project out of every Lanczos vector (FP64, dense J
+// order, vector l at psi + l * dim), nd of them.
+struct Deflation {
+    const double *psi = nullptr;
+    int nd = 0;
+};
+
 template <typename T>
-static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
+static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, const Deflation &dfl = Deflation())
 {
     const int64_t n = h->dim;
     const HvArgs args = hv_args(h);
@@ -342,10 +349,14 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     // the FP64 scratch of the residual (2 * npad * sizeof(T) >= npad * 8 bytes)
     DevBuf work(2 * sizeof(T) * (size_t)npad);
     T *vecs[2] = {work.as<T>(), work.as<T>() + npad};
-    DevBuf partials(sizeof(double) * (size_t)(3 * std::max(std::max(hb, plan64.nparts), sb) + 64));
-    DevBuf scal(sizeof(double) * 8 + sizeof(double) * 2 * (size_t)(max_iter + 1));
+    const int nd = dfl.nd;
+    const int db = defl_blocks(h->up.dim);
+    DevBuf partials(sizeof(double) *
+                    (size_t)(std::max(3 * std::max(std::max(hb, plan64.nparts), sb), nd * db) + 64));
+    DevBuf scal(sizeof(double) * (8 + kMaxDeflate + 1) + sizeof(double) * 2 * (size_t)(max_iter + 1));
     double *S = scal.as<double>();
-    double *hist = S + 8;
+    double *D = S + 8;  // projections psi_l . q of the deflated step
+    double *hist = D + kMaxDeflate + 1;
     PinnedBuf host(sizeof(double) * (2 * (size_t)(max_iter + 1) + 8));
     double *hh = host.as<double>();
     const double *given = o.start;
@@ -360,9 +371,30 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
         fail(HUBBARD_EINVAL, "start vector has zero or non-finite norm");
     const double inv_norm = 1.0 / std::sqrt(hh[0]);
 
+    // q <- P q (P = 1 - sum_l psi_l psi_l^T), after q <- q - c v when v is
+    // given; leaves the partial sums of |q|^2 (db of them) in `partials`.
+    auto project = [&](T *q, const T *v, const double *coef, int64_t ldq) {
+        const int nb = launch_defl_dots<T>(q, v, coef, dfl.psi, nd, n, h->up.dim, h->dn.dim, ldq,
+                                           partials.as<double>(), s);
+        launch_reduce(partials.as<double>(), nb, nb, nd, D, s);
+        launch_defl_update<T>(q, dfl.psi, D, nd, n, h->up.dim, h->dn.dim, ldq, partials.as<double>(), s);
+    };
+    // the same projection of an FP64 vector in dense J order (the accumulated psi)
+    auto project_psi = [&](double *q) {
+        const int nb = launch_defl_dots<double>(q, nullptr, nullptr, dfl.psi, nd, n, h->up.dim, h->dn.dim, h->dn.dim,
+                                                partials.as<double>(), s);
+        launch_reduce(partials.as<double>(), nb, nb, nd, D, s);
+        launch_defl_update<double>(q, dfl.psi, D, nd, n, h->up.dim, h->dn.dim, h->dn.dim, partials.as<double>(), s);
+    };
     auto start_pass = [&](T *C, T *P) {
         launch_start_fill<T>(given, seed, inv_norm, C, P, h->up.dim, h->dn.dim, ld, s);
-        launch_init_scalars(S, s);
+        if (nd > 0) {
+            // f_1 = P f / |P f|: the stored vector keeps its norm, S[0] = 1/|P f|
+            project(C, nullptr, nullptr, ld);
+            launch_reduce_step(partials.as<double>(), db, RED_START, S, nullptr, 0, s);
+        } else {
+            launch_init_scalars(S, s);
+        }
     };
     // Fused form (two-pass plans of large sectors): the update q - a_j f_j
     // is not a pass of its own.  The step leaves q = H v_j - b_j v_{j-1} in P,
@@ -370,7 +402,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     // b_{j+1} comes from the expanded norm (the reduction's RED_FUSED mode).
     // Small sectors, where a breakdown or an exhausted space is near, keep the
     // update pass and the norm of the stored vector.
-    const bool fused = plan.two_pass && plan.blk_grid > 0 && n >= kFusedMinDim;
+    const bool fused = nd == 0 && plan.two_pass && plan.blk_grid > 0 && n >= kFusedMinDim;
     auto hv_step = [&](T *C, T *P) {
         return launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, fused ? HV_FUSED : HV_LANCZOS, 0.0,
                              fused ? S : S + 1, partials.as<double>(), s);
@@ -381,6 +413,12 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
             return;
         }
         launch_reduce_step(partials.as<double>(), np, RED_DOT, S, hist, j0, s);
+        if (nd > 0) {
+            // deflated step: q = P (y - a_j f_j), then b_{j+1} = |q|
+            project(P, C, S + 3, ld);
+            launch_reduce_step(partials.as<double>(), db, RED_NORM, S, hist, j0, s);
+            return;
+        }
         launch_axpy_norm<T>(P, C, S + 3, npad, partials.as<double>(), sb, s);
         launch_reduce_step(partials.as<double>(), sb, RED_NORM, S, hist, j0, s);
     };
@@ -404,6 +442,13 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
     T *bufs[2] = {vecs[0], vecs[1]};
     auto t0 = std::chrono::steady_clock::now();
     start_pass(bufs[0], bufs[1]);
+    if (nd > 0) {
+        HUB_HIP(hipMemcpyAsync(hh, S, sizeof(double), hipMemcpyDeviceToHost, s));
+        HUB_HIP(hipStreamSynchronize(s));
+        // 1/|P f| of the unit start vector
+        if (!std::isfinite(hh[0]) || !(hh[0] > 0.0) || hh[0] > 1e8)
+            fail(HUBBARD_EINVAL, "the start vector lies in the span of the lower states");
+    }
     out.a.clear();
     out.b.clear();
     out.e.clear();
@@ -441,7 +486,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
                 stop = true;
                 break;
             }
-            if ((int64_t)j >= n) {
+            if ((int64_t)j >= n - nd) {
                 out.stop = HUBBARD_STOP_EXHAUSTED;
                 stop = true;
                 break;
@@ -483,6 +528,10 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out)
         if (j0 + 1 < m)
             step(C, P, j0);
     }
+    // the accumulated vector is projected once more, so that it is orthogonal
+    // to the lower states to rounding
+    if (nd > 0)
+        project_psi(o.psi);
     // normalise, sign so that <psi, f1> > 0
     launch_psi_stats(o.psi, given, seed, n, partials.as<double>(), sb, s);
     launch_reduce(partials.as<double>(), sb, sb, 2, S + 4, s);
@@ -512,6 +561,35 @@ void validate_opts(const hubbard_opts &o)
         fail(HUBBARD_EINVAL, "unknown precision");
 }
 
+static hubbard_result make_result(const LanczosOut &out, const hubbard_opts &o, double seconds, int status)
+{
+    hubbard_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.e0 = out.e0;
+    r.residual = o.psi ? out.residual : -1.0;
+    r.rayleigh = o.psi ? out.rayleigh : NAN;
+    if (o.psi) {
+        r.err_est = out.residual / std::fmax(1.0, std::fabs(out.e0));
+    } else {
+        // Lanczos estimate of |H psi - E0 psi| for the Ritz pair: b_{m+1} |y_m|
+        std::vector<double> y((size_t)out.m);
+        tridiag_lowest_vector(out.a.data(), out.b.data(), out.m, out.e0, y.data());
+        r.err_est = std::fabs(out.b.back() * y.back()) / std::fmax(1.0, std::fabs(out.e0));
+    }
+    r.seconds = seconds;
+    r.seconds_per_iter = out.m ? out.seconds_first / out.m : 0.0;
+    r.n_iter = out.m;
+    r.stop = out.stop;
+    r.status = status;
+    r.precision = o.precision;
+    return r;
+}
+
+static int status_of(const LanczosOut &out, const hubbard_opts &o)
+{
+    return (out.stop == HUBBARD_STOP_MAXITER && o.tol >= 0.0) ? HUBBARD_ENOCONV : HUBBARD_OK;
+}
+
 int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res)
 {
     validate_opts(o);
@@ -529,30 +607,62 @@ int lanczos_impl(hubbard *h, const hubbard_opts &o, hubbard_result *res)
         std::memcpy(o.b_out, out.b.data(), sizeof(double) * (size_t)out.m);
     if (o.e_out)
         std::memcpy(o.e_out, out.e.data(), sizeof(double) * (size_t)out.m);
-    const int status = (out.stop == HUBBARD_STOP_MAXITER && o.tol >= 0.0) ? HUBBARD_ENOCONV : HUBBARD_OK;
-    if (res) {
-        hubbard_result r;
-        std::memset(&r, 0, sizeof(r));
-        r.e0 = out.e0;
-        r.residual = o.psi ? out.residual : -1.0;
-        r.rayleigh = o.psi ? out.rayleigh : NAN;
-        if (o.psi) {
-            r.err_est = out.residual / std::fmax(1.0, std::fabs(out.e0));
-        } else {
-            // Lanczos estimate of |H psi - E0 psi| for the Ritz pair: b_{m+1} |y_m|
-            std::vector<double> y((size_t)out.m);
-            tridiag_lowest_vector(out.a.data(), out.b.data(), out.m, out.e0, y.data());
-            r.err_est = std::fabs(out.b.back() * y.back()) / std::fmax(1.0, std::fabs(out.e0));
-        }
-        r.seconds = std::chrono::duration<double>(t1 - t0).count();
-        r.seconds_per_iter = out.m ? out.seconds_first / out.m : 0.0;
-        r.n_iter = out.m;
-        r.stop = out.stop;
-        r.status = status;
-        r.precision = o.precision;
-        *res = r;
-    }
+    const int status = status_of(out, o);
+    if (res)
+        *res = make_result(out, o, std::chrono::duration<double>(t1 - t0).count(), status);
     return status;
+}
+
+// The k lowest eigenpairs one after another: state i is the ground state of
+// P_i H P_i, P_i projecting out psi_0..psi_{i-1} (Sec. 2.2 names the lowest
+// excited states as a goal of the method; the deflation by projection is this
+// library's choice of how to reach them with the same recurrence).
+int lowest_states_impl(hubbard *h, int k, const hubbard_opts &o, double *E, double *psi, hubbard_result *res)
+{
+    validate_opts(o);
+    if (k < 1 || k > kMaxDeflate + 1)
+        fail(HUBBARD_EINVAL, "k must lie in 1.." + std::to_string(kMaxDeflate + 1));
+    if ((int64_t)k > h->dim)
+        fail(HUBBARD_EINVAL, "k exceeds the sector dimension");
+    if (!E)
+        fail(HUBBARD_EINVAL, "E is NULL");
+    if (o.psi || o.a_out || o.b_out || o.e_out)
+        fail(HUBBARD_EINVAL, "opts.psi and the history arrays are not used by hubbard_lowest_states");
+    use_device(h);
+    std::unique_ptr<DevBuf> own;
+    double *base = psi;
+    if (!base) {
+        own.reset(new DevBuf(sizeof(double) * (size_t)k * (size_t)h->dim));
+        base = own->as<double>();
+    }
+    int worst = HUBBARD_OK;
+    for (int i = 0; i < k; i++) {
+        auto t0 = std::chrono::steady_clock::now();
+        // an independent start vector per state: a start shared by all of them
+        // has, inside a degenerate level, only the component that the first
+        // state of that level takes away, so the level's other vectors would be
+        // missed
+        hubbard_opts oi = o;
+        oi.seed = o.seed + (uint64_t)i;
+        if (i > 0)
+            oi.start = nullptr;
+        oi.psi = base + (size_t)i * (size_t)h->dim;
+        Deflation d;
+        d.psi = base;
+        d.nd = i;
+        LanczosOut out;
+        if (o.precision == HUBBARD_FP64)
+            run_lanczos<double>(h, oi, out, d);
+        else
+            run_lanczos<float>(h, oi, out, d);
+        auto t1 = std::chrono::steady_clock::now();
+        const int status = status_of(out, oi);
+        E[i] = out.e0;
+        if (res)
+            res[i] = make_result(out, oi, std::chrono::duration<double>(t1 - t0).count(), status);
+        worst = std::max(worst, status);
+    }
+    return worst;
 }
 
 }  // namespace hub
@@ -740,6 +850,17 @@ int hubbard_lanczos_ex(hubbard_h h, const hubbard_opts *opts, hubbard_result *re
         if (!opts || !res)
             fail(HUBBARD_EINVAL, "opts and res must not be NULL");
         return lanczos_impl(h, *opts, res);
+    });
+}
+
+int hubbard_lowest_states(hubbard_h h, int k, const hubbard_opts *opts, double *E, double *psi,
+                          hubbard_result *res)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (!opts)
+            fail(HUBBARD_EINVAL, "opts is NULL");
+        return lowest_states_impl(h, k, *opts, E, psi, res);
     });
 }
 

@@ -129,7 +129,7 @@ struct HvPlan {
     int nparts = 1;         // largest number of partial sums any launch writes
 };
 enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2, HV_FUSED = 3 };
-enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2, RED_FUSED = 3 };
+enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2, RED_FUSED = 3, RED_START = 4 };
 
 // HV_STORE:    y = H x
 // HV_LANCZOS:  y = alpha H x + beta y (in place), alpha = coef[0], beta = coef[1];
@@ -170,6 +170,16 @@ void launch_psi_stats(const double *psi, const double *given, uint64_t seed, int
                       hipStream_t s);
 void launch_scale(double *v, double c, int64_t n, hipStream_t s);
 void launch_reduce(const double *partials, int n, int stride, int count, double *out, hipStream_t s);
+// Most lower eigenvectors one deflated Lanczos run projects out.
+constexpr int kMaxDeflate = 15;
+// number of partial sums the two deflation kernels write per vector
+int defl_blocks(int64_t dim_up);
+template <typename T>
+int launch_defl_dots(T *q, const T *v, const double *coef, const double *psi, int nd, int64_t dim, int64_t dim_up,
+                     int64_t dim_dn, int64_t ld, double *partials, hipStream_t s);
+template <typename T>
+int launch_defl_update(T *q, const double *psi, const double *D, int nd, int64_t dim, int64_t dim_up, int64_t dim_dn,
+                       int64_t ld, double *partials, hipStream_t s);
 void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s);
 void launch_init_scalars(double *S, hipStream_t s);
 int stream_blocks(int64_t n);

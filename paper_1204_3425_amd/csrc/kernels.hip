@@ -341,6 +341,112 @@ template void launch_start_fill<double>(const double *, uint64_t, double, double
 template void launch_start_fill<float>(const double *, uint64_t, double, float *, float *, int64_t, int64_t, int64_t,
                                        hipStream_t);
 
+// ------------------------------------------------------------ deflation
+// The lower eigenvectors psi_0..psi_{nd-1} (FP64, dense J order, psi_l at
+// psi + l * dim) are projected out of every new Lanczos vector, so the
+// recurrence runs with P H P, P = 1 - sum_l psi_l psi_l^T, and its lowest Ritz
+// value approaches the next eigenvalue (Sec. 2.2: the lowest excited states).
+// Vectors in the internal layout are dim_up rows of dim_dn elements at stride
+// ld; the padding is left alone (it stays zero).
+
+// Optionally q = q - c v first (c = coef[0]: the q - a_j f_j update of Alg. 1),
+// then partial sums of psi_l . q for l < nd, stored at partials[l * grid + block].
+template <typename T>
+__global__ __launch_bounds__(256) void defl_dots_kernel(T *__restrict__ q, const T *__restrict__ v,
+                                                        const double *__restrict__ coef,
+                                                        const double *__restrict__ psi, int nd, int64_t dim,
+                                                        int64_t dim_up, int64_t dim_dn, int64_t ld,
+                                                        double *__restrict__ partials)
+{
+    __shared__ double red[4];
+    double acc[kMaxDeflate];
+#pragma unroll
+    for (int l = 0; l < kMaxDeflate; l++)
+        acc[l] = 0.0;
+    const T cs = v ? (T)coef[0] : (T)0;
+    ROW_LOOP(r, d, dim_up, dim_dn)
+    {
+        T x = q[r * ld + d];
+        if (v) {
+            x = x - cs * v[r * ld + d];
+            q[r * ld + d] = x;
+        }
+        const double xd = (double)x;
+        const double *p = psi + r * dim_dn + d;
+#pragma unroll
+        for (int l = 0; l < kMaxDeflate; l++)
+            if (l < nd)
+                acc[l] += xd * p[l * dim];
+    }
+    for (int l = 0; l < nd; l++) {
+        const double sl = block_sum(acc[l], red);
+        if (threadIdx.x == 0)
+            partials[(int64_t)l * gridDim.x + blockIdx.x] = sl;
+    }
+}
+
+// q = q - sum_l D[l] psi_l (rounded once to T), and partial sums of q.q.
+template <typename T>
+__global__ __launch_bounds__(256) void defl_update_kernel(T *__restrict__ q, const double *__restrict__ psi,
+                                                          const double *__restrict__ D, int nd, int64_t dim,
+                                                          int64_t dim_up, int64_t dim_dn, int64_t ld,
+                                                          double *__restrict__ partials)
+{
+    __shared__ double red[4];
+    double c[kMaxDeflate];
+#pragma unroll
+    for (int l = 0; l < kMaxDeflate; l++)
+        c[l] = l < nd ? D[l] : 0.0;
+    double acc = 0.0;
+    ROW_LOOP(r, d, dim_up, dim_dn)
+    {
+        double x = (double)q[r * ld + d];
+        const double *p = psi + r * dim_dn + d;
+#pragma unroll
+        for (int l = 0; l < kMaxDeflate; l++)
+            if (l < nd)
+                x -= c[l] * p[l * dim];
+        const T xt = (T)x;
+        q[r * ld + d] = xt;
+        acc += (double)xt * (double)xt;
+    }
+    const double sq = block_sum(acc, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = sq;
+}
+
+template <typename T>
+int launch_defl_dots(T *q, const T *v, const double *coef, const double *psi, int nd, int64_t dim, int64_t dim_up,
+                     int64_t dim_dn, int64_t ld, double *partials, hipStream_t s)
+{
+    const int nb = row_blocks(dim_up);
+    hipLaunchKernelGGL(defl_dots_kernel<T>, dim3(nb), dim3(256), 0, s, q, v, coef, psi, nd, dim, dim_up, dim_dn, ld,
+                       partials);
+    HUB_HIP(hipGetLastError());
+    return nb;
+}
+
+template <typename T>
+int launch_defl_update(T *q, const double *psi, const double *D, int nd, int64_t dim, int64_t dim_up, int64_t dim_dn,
+                       int64_t ld, double *partials, hipStream_t s)
+{
+    const int nb = row_blocks(dim_up);
+    hipLaunchKernelGGL(defl_update_kernel<T>, dim3(nb), dim3(256), 0, s, q, psi, D, nd, dim, dim_up, dim_dn, ld,
+                       partials);
+    HUB_HIP(hipGetLastError());
+    return nb;
+}
+template int launch_defl_dots<double>(double *, const double *, const double *, const double *, int, int64_t, int64_t,
+                                      int64_t, int64_t, double *, hipStream_t);
+template int launch_defl_dots<float>(float *, const float *, const double *, const double *, int, int64_t, int64_t,
+                                     int64_t, int64_t, double *, hipStream_t);
+template int launch_defl_update<double>(double *, const double *, const double *, int, int64_t, int64_t, int64_t,
+                                        int64_t, double *, hipStream_t);
+template int launch_defl_update<float>(float *, const double *, const double *, int, int64_t, int64_t, int64_t,
+                                       int64_t, double *, hipStream_t);
+
+int defl_blocks(int64_t dim_up) { return row_blocks(dim_up); }
+
 // psi += y_j * (1/s) * v, where v holds s f_j and 1/s is the device scalar
 // coef[0] (the ground-state vector sum_j y_j f_j of the replayed recurrence).
 template <typename T>
@@ -415,6 +521,8 @@ void launch_scale(double *v, double c, int64_t n, hipStream_t s)
 // mode RED_NORM (after that update): b_{j+1} = sqrt(sum); hist[2j+1] = b_{j+1};
 //   the roles of the two vectors swap, so the next H.v gets
 //   alpha = 1/b_{j+1}, beta = -b_{j+1} * S[0] (old 1/s), and S[0] = 1/b_{j+1}.
+// mode RED_START (after the start vector was projected): S = {1/s, 1/s, 0, 0}
+//   with s = sqrt(sum), the norm of the stored start vector.
 // mode RED_FUSED (after a fused step, partials [3][n] = shares of y.x, y.y,
 //   x.x with x = X_j, the stored vector of norm s, and y = H X_j / s - b_j v_{j-1}):
 //   a_j = (y.x) / s, c = a_j / s, and the norm of the next vector
@@ -462,6 +570,12 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
             const double a = s * S[0];
             S[3] = a * S[0];
             hist[2 * j] = a;
+        } else if (mode == RED_START) {
+            const double b = sqrt(s);
+            S[0] = b > 0.0 ? 1.0 / b : 0.0;
+            S[1] = S[0];
+            S[2] = 0.0;
+            S[3] = 0.0;
         } else {
             const double b = sqrt(s);
             hist[2 * j + 1] = b;

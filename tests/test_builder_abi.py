@@ -189,3 +189,28 @@ def test_admission_plan_first_fit():
         used = int(rng.integers(0, 100))
         take = hb.hubbard_admission_plan(fp, 100, used, int(rng.integers(0, 6)))
         assert used + sum(f for f, t in zip(fp, take) if t) <= max(100, used)
+
+
+def test_lowest_states_validates_before_touching_the_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("checks the no-device return code; run only where no GPU is present")
+    h = hb.hubbard_build(2, [(0, 1)], 1, 1, 1.0, 2.0)  # dim 4
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    lib.hubbard_lowest_states.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(hb.hubbard_opts),
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    o = hb.hubbard_opts()
+    o.tol, o.max_iter, o.precision, o.seed = 1e-12, 50, hb.HUBBARD_FP64, 1
+    E = np.zeros(17)
+    for k in (0, -1, 5, 17):  # out of 1..16 or above dim = 4
+        assert lib.hubbard_lowest_states(h.ptr, k, ctypes.byref(o), E.ctypes.data, None, None) == hb.HUBBARD_EINVAL
+    assert lib.hubbard_lowest_states(h.ptr, 2, None, E.ctypes.data, None, None) == hb.HUBBARD_EINVAL
+    assert lib.hubbard_lowest_states(h.ptr, 2, ctypes.byref(o), None, None, None) == hb.HUBBARD_EINVAL
+    o.psi = 4096  # opts.psi is not how the vectors are returned
+    assert lib.hubbard_lowest_states(h.ptr, 2, ctypes.byref(o), E.ctypes.data, None, None) == hb.HUBBARD_EINVAL
+    o.psi = None
+    o.max_iter = 0
+    assert lib.hubbard_lowest_states(h.ptr, 2, ctypes.byref(o), E.ctypes.data, None, None) == hb.HUBBARD_EINVAL
+    o.max_iter = 50
+    # valid arguments reach the device check
+    assert lib.hubbard_lowest_states(h.ptr, 2, ctypes.byref(o), E.ctypes.data, None, None) == hb.HUBBARD_EDEVICE

@@ -1,0 +1,176 @@
+"""GPU parity of the lowest k eigenpairs (hubbard_lowest_states) against the
+FP64 oracle's dense eigenproblem (Sec. 2.2: the ground state and the lowest
+excited states).
+
+What is unique is compared element by element, the rest is checked for
+validity:
+  * eigenvalues: |E_i - w_i| <= 1e-10 max(1, |w_i|) in FP64 and 1e-6 in mixed
+    precision, w the oracle's ascending spectrum with multiplicity;
+  * eigenvectors: an eigenvector is unique only up to sign and, inside a
+    degenerate level, up to a rotation of the level.  Each psi_i must lie in the
+    oracle's eigenspace of its level: by the Davis-Kahan bound the distance is
+    at most r_i / delta_i, with r_i = |H psi_i - E_i psi_i| (computed here with the
+    oracle's H) and delta_i the oracle's gap from that level to the rest of the
+    spectrum; the test allows twice that.  The psi_i are orthonormal to 1e-12
+    (each is projected against the lower ones in FP64 at the end), the residual
+    the library reports equals the oracle's to rounding, and a non-degenerate
+    psi_i has <psi_i, f1^(i)> > 0, f1^(i) the seeded start vector of seed + i.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+
+torch = pytest.importorskip("torch")
+hb = pytest.importorskip("paper_1204_3425_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SEED = workload.BASE_SEED
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+CASES = [
+    # name, sites, edges, n_up, n_dn, t, U, k
+    ("ring8_3u3d_U4", 8, workload.ring(8), 3, 3, 1.0, 4.0, 6),
+    # rows of 462 elements: two strides of a 256-thread workgroup with a ragged tail
+    ("ring11_1u5d_U4", 11, workload.ring(11), 1, 5, 1.0, 4.0, 5),
+    ("torus2x4_3u2d_U6", 8, workload.torus(2, 4), 3, 2, 1.0, 6.0, 5),
+    # t = 0: a 20-fold degenerate lowest level, each state ends in a breakdown
+    ("ring6_atomic_3u3d", 6, workload.ring(6), 3, 3, 0.0, 2.5, 8),
+    # U = 0: free fermions, degenerate levels
+    ("ring6_free_2u3d", 6, workload.ring(6), 2, 3, 0.8, 0.0, 10),
+    # k = dim: the last state is the one vector left
+    ("dimer_1u1d_U3", 2, [(0, 1)], 1, 1, 1.3, 3.0, 4),
+]
+
+
+def _gpu_states(sites, edges, nu, nd, t, U, k, precision, tol, max_iter=600, want_psi=True):
+    h = hb.hubbard_build(sites, edges, nu, nd, t, U)
+    psi = torch.zeros((k, h.dim), dtype=torch.float64, device=DEV) if want_psi else None
+    E, res = hb.hubbard_lowest_states(h, k, tol=tol, max_iter=max_iter, precision=precision, seed=SEED, psi=psi)
+    torch.cuda.synchronize()
+    return h, E, res, (psi.cpu().numpy() if want_psi else None)
+
+
+def _check_against_oracle(m, E, res, Psi, etol):
+    w_all, V_all = m.lowest_states(m.dim)
+    k = len(E)
+    scale = np.maximum(1.0, np.abs(w_all[:k]))
+    assert np.all(np.abs(E - w_all[:k]) <= etol * scale), (E, w_all[:k])
+    # orthonormal
+    G = Psi @ Psi.T
+    assert np.abs(G - np.eye(k)).max() <= 1e-12
+    spread = max(1.0, w_all[-1] - w_all[0])
+    for i in range(k):
+        v = Psi[i]
+        r = np.linalg.norm(m.apply(v) - E[i] * v)
+        # the reported residual is the FP64 |H psi - E psi| of this same vector
+        assert abs(res[i]["residual"] - r) <= 1e-12 * spread, (i, res[i]["residual"], r)
+        # eigenspace of the level of w_i in the oracle's full spectrum
+        lvl = np.abs(w_all - w_all[i]) <= 1e-9 * spread
+        rest = w_all[~lvl]
+        gap = np.min(np.abs(rest - w_all[i])) if rest.size else np.inf
+        Vc = V_all[lvl]  # the level's oracle eigenvectors, one per row
+        dist = np.linalg.norm(v - Vc.T @ (Vc @ v))
+        assert dist <= 2.0 * r / gap + 1e-11, (i, dist, r, gap)
+        if lvl.sum() == 1:
+            # state i starts from the seeded vector of seed + i
+            assert v @ oracle.start_vector(SEED + i, m.dim, normalise=False) > 0.0
+    return w_all
+
+
+@pytest.mark.parametrize("name,sites,edges,nu,nd,t,U,k", CASES, ids=[c[0] for c in CASES])
+def test_lowest_states_fp64_parity(name, sites, edges, nu, nd, t, U, k):
+    _say("lowest_states fp64", name, "k", k)
+    h, E, res, Psi = _gpu_states(sites, edges, nu, nd, t, U, k, hb.HUBBARD_FP64, tol=1e-14)
+    assert all(r["status"] == hb.HUBBARD_OK for r in res), [r["stop"] for r in res]
+    m = oracle.Model(sites, edges, nu, nd, t, U)
+    _check_against_oracle(m, E, res, Psi, 1e-10)
+
+
+def test_lowest_states_dimer_closed_form():
+    """The four dimer levels of Sec. 1's model in closed form."""
+    t, U = 1.3, 3.0
+    _, E, _, _ = _gpu_states(2, [(0, 1)], 1, 1, t, U, 4, hb.HUBBARD_FP64, tol=1e-14)
+    r = math.sqrt(U * U + 16 * t * t)
+    want = np.sort([0.0, U, (U - r) / 2, (U + r) / 2])
+    assert np.allclose(E, want, rtol=0, atol=1e-12)
+
+
+def test_lowest_states_mixed_parity():
+    name, sites, edges, nu, nd, t, U, k = CASES[0]
+    _say("lowest_states mixed", name)
+    h, E, res, Psi = _gpu_states(sites, edges, nu, nd, t, U, 4, hb.HUBBARD_MIXED, tol=1e-10)
+    m = oracle.Model(sites, edges, nu, nd, t, U)
+    w = m.lowest_states(4)[0]
+    assert np.all(np.abs(E - w) <= 1e-6 * np.maximum(1.0, np.abs(w))), (E, w)
+    assert np.abs(Psi @ Psi.T - np.eye(4)).max() <= 1e-12
+    for i in range(4):
+        assert res[i]["residual"] <= 1e-2
+
+
+def test_first_state_is_the_ground_state_solve():
+    """k = 1 runs exactly the single ground-state solve: same E0, same psi."""
+    p = workload.ring8()
+    h, E, res, Psi = _gpu_states(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U, 1, hb.HUBBARD_FP64, tol=1e-12,
+                                 max_iter=300)
+    psi = torch.zeros(h.dim, dtype=torch.float64, device=DEV)
+    r = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=SEED, psi=psi)
+    torch.cuda.synchronize()
+    assert E[0] == r["E0"] and res[0]["n_iter"] == r["n_iter"]
+    assert np.array_equal(Psi[0], psi.cpu().numpy())
+
+
+def test_states_without_psi_match():
+    """psi = NULL (the library holds the vectors) gives the same energies."""
+    name, sites, edges, nu, nd, t, U, k = CASES[2]
+    _, E1, _, _ = _gpu_states(sites, edges, nu, nd, t, U, k, hb.HUBBARD_FP64, tol=1e-14)
+    _, E2, res2, _ = _gpu_states(sites, edges, nu, nd, t, U, k, hb.HUBBARD_FP64, tol=1e-14, want_psi=False)
+    assert np.array_equal(E1, E2)
+    assert all(r["residual"] >= 0.0 for r in res2)
+
+
+def test_lowest_states_errors():
+    h = hb.hubbard_build(2, [(0, 1)], 1, 1, 1.0, 2.0)
+    for k in (0, 5, 17):
+        with pytest.raises(hb.HubbardError) as ei:
+            hb.hubbard_lowest_states(h, k)
+        assert ei.value.code == hb.HUBBARD_EINVAL
+
+
+def test_lowest_states_large_sector_properties():
+    """14-site ring at half filling (dim 11.8M, the two-pass H.v): state 0 is
+    the ground-state solve bit for bit; the psi_i are orthonormal (to the
+    rounding of a dot product over dim terms);
+    on 64 sampled rows the oracle's (H psi_i)[J] agrees with E_i psi_i[J] within
+    the residual the library reports; E_0 <= E_1 <= E_2."""
+    p = workload.ring14()
+    k = 3
+    _say("lowest_states", p.name, "k", k)
+    h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    psi = torch.zeros((k, h.dim), dtype=torch.float64, device=DEV)
+    E, res = hb.hubbard_lowest_states(h, k, tol=1e-12, max_iter=400, precision=hb.HUBBARD_FP64, seed=SEED, psi=psi)
+    torch.cuda.synchronize()
+    _say("E", E, "iters", [r["n_iter"] for r in res], "residuals", [r["residual"] for r in res])
+    r0 = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=400, precision=hb.HUBBARD_FP64, seed=SEED)
+    assert E[0] == r0["E0"]
+    G = (psi @ psi.T).cpu().numpy()
+    # a dot product of dim terms rounds to about sqrt(dim) ulp
+    assert np.abs(G - np.eye(k)).max() <= 1e-14 * math.sqrt(h.dim)
+    assert E[0] <= E[1] + 1e-10 and E[1] <= E[2] + 1e-10
+    m = oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    rows = np.random.default_rng(SEED).choice(h.dim, 64, replace=False)
+    Psi = psi.cpu().numpy()
+    for i in range(k):
+        assert res[i]["residual"] <= 1e-4 * max(1.0, abs(E[i]))
+        hv = m.apply_rows(Psi[i], rows)
+        assert np.all(np.abs(hv - E[i] * Psi[i][rows]) <= res[i]["residual"] + 1e-12)
+        assert res[i]["rayleigh"] == pytest.approx(E[i], rel=1e-10)
