@@ -7,7 +7,8 @@ with the GPU library (``paper_1204_3425_amd``) and never imports it.
 The arithmetic lives in ``hubbard_oracle.c`` (plain C, built with gcc -O2, one
 thread); this module only marshals arguments, except ``Model.lowest_states``,
 which hands the dense H built from that C code to numpy's symmetric
-eigen-solver.  Every function cites the part
+eigen-solver, and ``Model.observables``, which sums psi^2 against the
+configuration bits with numpy.  Every function cites the part
 of Siro & Harju (arXiv:1204.3425) it follows.
 """
 from __future__ import annotations
@@ -210,6 +211,30 @@ class Model:
         assert 1 <= k <= self.dim
         w, v = np.linalg.eigh(self.dense())
         return w[:k].copy(), np.ascontiguousarray(v[:, :k].T)
+
+    def observables(self, psi: np.ndarray):
+        """Site occupations of the state psi, <psi|O|psi> / <psi|psi> (Sec. 1:
+        n_{i sigma} = c+_{i sigma} c_{i sigma}, which is diagonal in the basis of
+        Sec. 2.1: bit i of the spin's configuration word).  Returns a dict:
+          dens[s, i]     = <n_{i s}>,                  s = 0 up, 1 down
+          corr[k, i, j]  = <n_{i a} n_{j b}>,          (a, b) = (up, up), (dn, dn), (up, dn) for k = 0, 1, 2
+          docc           = <sum_i n_{i up} n_{i dn}>   (the operator of the interaction term of eq. H)
+        Every term is the sum over J of psi_J^2 times the product of the bits,
+        written with matrix products over the dim_up x dim_dn view of psi^2."""
+        psi = np.asarray(psi, dtype=np.float64)
+        assert psi.shape == (self.dim,)
+        ns = self.ns
+        su, _, _, _ = self.table(0)
+        sd, _, _, _ = self.table(1)
+        bu = ((su[:, None] >> np.arange(ns)) & 1).astype(np.float64)  # dim_up x ns
+        bd = ((sd[:, None] >> np.arange(ns)) & 1).astype(np.float64)  # dim_dn x ns
+        W = (psi * psi).reshape(self.dim_up, self.dim_dn)
+        norm = W.sum()
+        R = W.sum(axis=1)                       # weight of each up configuration
+        Q = W.sum(axis=0)                       # weight of each down configuration
+        dens = np.stack([bu.T @ R, bd.T @ Q]) / norm
+        corr = np.stack([(bu * R[:, None]).T @ bu, (bd * Q[:, None]).T @ bd, bu.T @ W @ bd]) / norm
+        return {"dens": dens, "corr": corr, "docc": float(np.trace(corr[2])), "norm2": float(norm)}
 
     def lanczos(self, f1: np.ndarray, tol: float = 1e-12, max_iter: int = 300, want_psi: bool = False):
         """Alg. 1 from the unit start vector f1; returns a dict with a_j, b_{j+1},

@@ -388,3 +388,79 @@ def test_lowest_states_trace_and_ordering():
     ref = _atomic_spectrum(ns, nu, nd, U).sum()
     assert w.sum() == pytest.approx(ref, rel=1e-12)
     _check_eigvecs(m, w, V)
+
+
+# ------------------------------------------------------------------ site observables (Sec. 1, eq. H)
+
+def _ground(ns, edges, nu, nd, t, U):
+    m = oracle.Model(ns, edges, nu, nd, t, U)
+    w, V = m.lowest_states(2)
+    return m, w, V[0]
+
+
+@pytest.mark.parametrize("U", [0.5, 4.0])
+@pytest.mark.parametrize("kind", ["torus2x3", "chain6"])
+def test_double_occupancy_is_dE0_dU(kind, U):
+    """Hellmann-Feynman: for a non-degenerate ground state dE0/dU = <sum_i n_i,up n_i,dn>,
+    checked against a central difference of the dense E0."""
+    ns, edges = (6, workload.torus(2, 3)) if kind == "torus2x3" else (6, workload.chain(6))
+    nu, nd, t = (3, 3, 1.0) if kind == "torus2x3" else (3, 2, 1.0)
+    m, w, v = _ground(ns, edges, nu, nd, t, U)
+    assert w[1] - w[0] > 1e-3  # non-degenerate
+    d = 1e-4
+    e = [oracle.Model(ns, edges, nu, nd, t, U + s * d).lowest_states(1)[0][0] for s in (-1, 1)]
+    assert m.observables(v)["docc"] == pytest.approx((e[1] - e[0]) / (2 * d), abs=1e-7)
+
+
+@pytest.mark.parametrize("U", [0.0, 2.0, 9.0])
+def test_double_occupancy_dimer_closed_form(U):
+    """Dimer ground state: D = (1 - U / sqrt(U^2 + 16 t^2)) / 2, the U-derivative of
+    E0 = (U - sqrt(U^2 + 16 t^2)) / 2."""
+    t = 0.7
+    m, _, v = _ground(2, [(0, 1)], 1, 1, t, U)
+    o = m.observables(v)
+    assert o["docc"] == pytest.approx((1 - U / math.sqrt(U * U + 16 * t * t)) / 2, abs=1e-13)
+    assert np.allclose(o["dens"], 0.5, atol=1e-13)
+
+
+def test_free_chain_densities_and_factorisation():
+    """U = 0 on an open chain (non-degenerate ground state): <n_i sigma> = sum over the
+    N_sigma lowest orbitals of phi_k(i)^2, phi_k(i) = sqrt(2/(L+1)) sin(pi k (i+1) / (L+1)),
+    and up and down electrons are independent: <n_i,up n_j,dn> = <n_i,up><n_j,dn>."""
+    L, nu, nd = 7, 3, 2
+    m, w, v = _ground(L, workload.chain(L), nu, nd, 1.0, 0.0)
+    assert w[1] - w[0] > 1e-3
+    o = m.observables(v)
+    phi = lambda k, i: math.sqrt(2 / (L + 1)) * math.sin(math.pi * k * (i + 1) / (L + 1))
+    for s, n in ((0, nu), (1, nd)):
+        ref = [sum(phi(k, i) ** 2 for k in range(1, n + 1)) for i in range(L)]
+        assert np.allclose(o["dens"][s], ref, atol=1e-12)
+    assert np.allclose(o["corr"][2], np.outer(o["dens"][0], o["dens"][1]), atol=1e-12)
+
+
+def test_atomic_limit_has_no_double_occupancy():
+    """t = 0, U > 0, N_up + N_dn <= Ns: every ground state has no doubly occupied site."""
+    m = oracle.Model(6, workload.ring(6), 3, 2, 0.0, 3.0)
+    w, V = m.lowest_states(5)
+    for v in V:
+        assert m.observables(v)["docc"] == 0.0
+
+
+def test_observable_sum_rules():
+    """sum_i <n_i s> = N_s; <n_i s n_i s> = <n_i s>; sum_j <n_i a n_j b> = N_b <n_i a>;
+    the (up, up) and (dn, dn) blocks are symmetric; an unnormalised psi gives the same values."""
+    ns, nu, nd = 6, 3, 2
+    m = oracle.Model(ns, workload.torus(2, 3), nu, nd, 1.0, 3.0)
+    v = RNG.uniform(-1, 1, m.dim)  # any state, not an eigenvector
+    o = m.observables(v)
+    assert o["dens"][0].sum() == pytest.approx(nu, abs=1e-12)
+    assert o["dens"][1].sum() == pytest.approx(nd, abs=1e-12)
+    for k, (a, b, nb) in enumerate(((0, 0, nu), (1, 1, nd), (0, 1, nd))):
+        C = o["corr"][k]
+        assert np.allclose(C.sum(axis=1), nb * o["dens"][a], atol=1e-12)
+        if a == b:
+            assert np.allclose(np.diag(C), o["dens"][a], atol=1e-13)
+            assert np.allclose(C, C.T, atol=1e-13)
+    assert np.allclose(o["corr"][2].sum(axis=0), nu * o["dens"][1], atol=1e-12)
+    o2 = m.observables(3.0 * v)
+    assert np.allclose(o2["corr"], o["corr"], atol=1e-14) and o2["docc"] == pytest.approx(o["docc"], abs=1e-14)
