@@ -16,7 +16,8 @@ Printed JSON line (one):
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counts when they were taken
                  on the current kernel sources, else null
   cpu_baseline   the sequential FP64 oracle on one host core, bounded sample
-  excited        the k lowest states of the same sector (hubbard_lowest_states)
+  excited        the k lowest states of the same sector (hubbard_lowest_states) and
+                 the site observables of its ground state (hubbard_observables)
 
 Other modes:
   --calibrate-copy           also run one device copy of known size (for counter scaling)
@@ -216,11 +217,24 @@ def bench_excited(hb, torch, p, k, tol):
                                       psi=psi)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    G = (psi @ psi.T).cpu()
-    ortho = float((G - torch.eye(k, dtype=G.dtype)).abs().max())
-    bench_excited.vectors[p.name] = (p, E, psi.cpu().numpy(), [r["residual"] for r in res])
+    # Gram matrix by pairwise dot products (a k x dim by dim x k GEMM is far slower)
+    ortho = max(abs(float(torch.dot(psi[i], psi[j])) - (1.0 if i == j else 0.0))
+                for i in range(k) for j in range(i + 1))
+    # site observables of the ground state (one pass over psi_0; the call is synchronous)
+    t_obs = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ob = hb.hubbard_observables(h, psi[0])
+        t_obs.append(time.perf_counter() - t0)
+    t_obs = sorted(t_obs)[len(t_obs) // 2]
+    bench_excited.vectors[p.name] = (p, E, psi.cpu().numpy(), [r["residual"] for r in res], ob)
     del psi
+    obs = {"seconds_median_of_5": round(t_obs, 6), "psi_read_gbs": round(p.dim * 8 / t_obs / 1e9, 1),
+           "docc": ob["docc"], "interaction_energy_U_docc": p.U * ob["docc"],
+           "dens_range": [float(ob["dens"].min()), float(ob["dens"].max())]}
     return {"workload": p.name, "dim": p.dim, "k": k, "tol": tol, "seconds": round(dt, 3),
+            "observables_state0": obs,
             "E": [float(e) for e in E], "gap_E1_minus_E0": float(E[1] - E[0]) if k > 1 else None,
             "iters": [r["n_iter"] for r in res], "stop": [r["stop"] for r in res],
             "ms_per_iter_first_pass": [round(r["seconds_per_iter"] * 1e3, 4) for r in res],
@@ -234,26 +248,37 @@ def oracle_excited_check():
     """The oracle beside the excited-state leg: for the 8-site ring its dense
     eigenproblem (timed) against the GPU energies; for the 4x4 lattice, whose
     spectrum the oracle cannot reach, (H psi_i)[J] from the oracle on 64
-    sampled rows against E_i psi_i[J], within the residual the GPU reports."""
+    sampled rows against E_i psi_i[J], within the residual the GPU reports.
+    On both, the oracle's site observables of the GPU's psi_0 (timed) against
+    the GPU's."""
     import numpy as np
     import oracle
     out = {}
-    for name, (p, E, Psi, resid) in bench_excited.vectors.items():
+    for name, (p, E, Psi, resid, ob) in bench_excited.vectors.items():
         m = oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
         k = len(E)
+        t0 = time.perf_counter()
+        oo = m.observables(Psi[0])
+        t_oo = time.perf_counter() - t0
+        obs = {"oracle_seconds": round(t_oo, 3),
+               "max_abs_err_vs_oracle": float("%.3g" % max(np.abs(ob["dens"] - oo["dens"]).max(),
+                                                           np.abs(ob["corr"] - oo["corr"]).max(),
+                                                           abs(ob["docc"] - oo["docc"])))}
         if p.dim <= 6000:
             t0 = time.perf_counter()
             w = m.lowest_states(k)[0]
             dt = time.perf_counter() - t0
             err = float(np.max(np.abs(E - w) / np.maximum(1.0, np.abs(w))))
-            out[name] = {"oracle_seconds": round(dt, 3), "E_max_rel_err_vs_oracle": float("%.3g" % err)}
+            out[name] = {"oracle_seconds": round(dt, 3), "E_max_rel_err_vs_oracle": float("%.3g" % err),
+                         "observables_state0": obs}
         else:
             rows = np.random.default_rng(p.seed).choice(p.dim, 64, replace=False)
             worst = 0.0
             for i in range(k):
                 hv = m.apply_rows(Psi[i], rows)
                 worst = max(worst, float(np.max(np.abs(hv - E[i] * Psi[i][rows]))) / max(resid[i], 1e-300))
-            out[name] = {"sampled_rows": 64, "max_row_error_over_residual": float("%.3g" % worst)}
+            out[name] = {"sampled_rows": 64, "max_row_error_over_residual": float("%.3g" % worst),
+                         "observables_state0": obs}
         del m
     return out
 
@@ -412,7 +437,8 @@ def stored_traffic(dim):
 def _kernel_family(name):
     for fam in ("batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "batch_init_state_kernel",
                 "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel",
-                "axpy_norm_kernel",
+                "axpy_norm_kernel", "defl_dots_kernel", "defl_update_kernel", "obs_accumulate_kernel",
+                "obs_sum_groups_kernel", "obs_sum_kernel", "psi_stats_kernel", "scale_kernel",
                 "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
                 "psi_acc_kernel", "copyBuffer", "elementwise"):
         if fam in name:

@@ -192,6 +192,24 @@ int hubbard_lanczos_ex(hubbard_h h, const hubbard_opts *opts, hubbard_result *re
 int hubbard_lowest_states(hubbard_h h, int k, const hubbard_opts *opts, double *E, double *psi,
                           hubbard_result *res);
 
+/* Site occupations of a state and their correlations, <psi|O|psi> / <psi|psi>
+ * for the number operators n_{i sigma} of eq. H (Sec. 1), which are diagonal in
+ * the configuration basis (Sec. 2.1: bit i of a spin's word is n_i of that
+ * spin).  One pass over psi on the device; the sums are FP64 and reduced in a
+ * fixed order.
+ *   psi: device FP64 array of dim elements (J order), any non-zero norm.
+ *   dens: NULL or host array[2 * sites]: <n_{i up}> at i, <n_{i dn}> at sites + i.
+ *   corr: NULL or host array[3 * sites * sites], row-major blocks:
+ *     <n_{i up} n_{j up}> at i * sites + j, <n_{i dn} n_{j dn}> at
+ *     sites^2 + i * sites + j, <n_{i up} n_{j dn}> at 2 sites^2 + i * sites + j;
+ *     the diagonal of the last block is the double occupancy of each site.
+ *   docc: NULL or host scalar: D = <sum_i n_{i up} n_{i dn}>, so that the
+ *     interaction energy of eq. H is U * D (and, for a ground state,
+ *     D = dE0/dU).
+ * Errors: EINVAL (psi NULL, or zero or non-finite norm), ENOMEM, EDEVICE.
+ * Synchronous on the handle's stream. */
+int hubbard_observables(hubbard_h h, const double *psi, double *dens, double *corr, double *docc);
+
 /* Sizes of the handle's sector and tables. */
 int hubbard_info(hubbard_h h, hubbard_info_t *info);
 

@@ -116,6 +116,7 @@ def _load():
         "hubbard_start_raw": [u64, i64, vp, vp],
         "hubbard_lanczos_batch": [vp, i32, ctypes.POINTER(hubbard_opts), ctypes.POINTER(hubbard_result)],
         "hubbard_lowest_states": [vp, i32, ctypes.POINTER(hubbard_opts), vp, vp, ctypes.POINTER(hubbard_result)],
+        "hubbard_observables": [vp, vp, vp, vp, vp],
         "hubbard_server_create": [ctypes.c_size_t, i32, ctypes.POINTER(vp)],
         "hubbard_server_submit": [vp, ctypes.POINTER(hubbard_request), ctypes.POINTER(ctypes.c_uint64)],
         "hubbard_server_poll": [vp, ctypes.POINTER(hubbard_completion), i32, ctypes.POINTER(ctypes.c_int), i32],
@@ -344,6 +345,21 @@ def hubbard_lowest_states(h: Handle, k: int, tol=1e-12, max_iter=300, precision=
     _check(_lib.hubbard_lowest_states(h, int(k), ctypes.byref(o), E.ctypes.data, pp, res),
            "hubbard_lowest_states", allow=(HUBBARD_OK, HUBBARD_ENOCONV))
     return E[:k].copy(), [_result_dict(res[i], None) for i in range(int(k))]
+
+
+def hubbard_observables(h: Handle, psi, stream="current") -> dict:
+    """Site occupations of the state psi (device FP64 tensor of dim elements):
+    dens (2, sites), corr (3, sites, sites) for (up,up), (dn,dn), (up,dn), and
+    the double occupancy D."""
+    if stream == "current":
+        hubbard_set_stream(h, _current_stream())
+    n = h.sites
+    dens = np.zeros(2 * n)
+    corr = np.zeros(3 * n * n)
+    d = ctypes.c_double()
+    _check(_lib.hubbard_observables(h, _dev_ptr(psi, "float64", h.dim, "psi"), dens.ctypes.data, corr.ctypes.data,
+                                    ctypes.byref(d)), "hubbard_observables")
+    return {"dens": dens.reshape(2, n), "corr": corr.reshape(3, n, n), "docc": d.value}
 
 
 def hubbard_info(h: Handle) -> dict:

@@ -13,7 +13,8 @@ ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
-SOURCES = ["builder.cpp", "tridiag.cpp", "capi.cpp", "kernels.hip", "hv.hip", "batch.hip", "batch.cpp", "server.cpp"]
+SOURCES = ["builder.cpp", "tridiag.cpp", "capi.cpp", "kernels.hip", "hv.hip", "batch.hip", "batch.cpp", "server.cpp",
+           "observables.hip"]
 
 
 def build(verbose: bool = False) -> str:

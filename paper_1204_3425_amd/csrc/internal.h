@@ -170,6 +170,15 @@ void launch_psi_stats(const double *psi, const double *given, uint64_t seed, int
                       hipStream_t s);
 void launch_scale(double *v, double c, int64_t n, hipStream_t s);
 void launch_reduce(const double *partials, int n, int stride, int count, double *out, hipStream_t s);
+// observables.hip: unnormalised sums UU, DD, C (NS x NS each, NS = obs_ns_max)
+// and the norm of psi^2 into out[3 * NS * NS + 1]; part holds
+// obs_partial_count blocks of that size (the workgroups' partials and the
+// group sums of the reduction).
+int obs_ns_max(int sites);
+int obs_partial_count(int ns, int64_t dim_up, int64_t dim_dn);
+void launch_observables(const double *psi, const uint32_t *states_up, const uint32_t *states_dn, int ns,
+                        int64_t dim_up, int64_t dim_dn, double *part, double *out, hipStream_t s);
+
 // Most lower eigenvectors one deflated Lanczos run projects out.
 constexpr int kMaxDeflate = 15;
 // number of partial sums the two deflation kernels write per vector

@@ -214,3 +214,15 @@ def test_lowest_states_validates_before_touching_the_device():
     o.max_iter = 50
     # valid arguments reach the device check
     assert lib.hubbard_lowest_states(h.ptr, 2, ctypes.byref(o), E.ctypes.data, None, None) == hb.HUBBARD_EDEVICE
+
+
+def test_observables_validates_before_touching_the_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("checks the no-device return code; run only where no GPU is present")
+    h = hb.hubbard_build(4, workload.ring(4), 2, 2, 1.0, 2.0)
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    lib.hubbard_observables.argtypes = [ctypes.c_void_p] * 5
+    assert lib.hubbard_observables(h.ptr, None, None, None, None) == hb.HUBBARD_EINVAL
+    assert lib.hubbard_observables(None, 4096, None, None, None) == hb.HUBBARD_EINVAL
+    assert lib.hubbard_observables(h.ptr, 4096, None, None, None) == hb.HUBBARD_EDEVICE
