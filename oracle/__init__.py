@@ -7,8 +7,9 @@ with the GPU library (``paper_1204_3425_amd``) and never imports it.
 The arithmetic lives in ``hubbard_oracle.c`` (plain C, built with gcc -O2, one
 thread); this module only marshals arguments, except ``Model.lowest_states``,
 which hands the dense H built from that C code to numpy's symmetric
-eigen-solver, and ``Model.observables``, which sums psi^2 against the
-configuration bits with numpy.  Every function cites the part
+eigen-solver, ``Model.observables``, which sums psi^2 against the
+configuration bits with numpy, and ``Model.propagate``, which builds
+exp(-i H t) from that same eigen-solver.  Every function cites the part
 of Siro & Harju (arXiv:1204.3425) it follows.
 """
 from __future__ import annotations
@@ -235,6 +236,16 @@ class Model:
         dens = np.stack([bu.T @ R, bd.T @ Q]) / norm
         corr = np.stack([(bu * R[:, None]).T @ bu, (bd * Q[:, None]).T @ bd, bu.T @ W @ bd]) / norm
         return {"dens": dens, "corr": corr, "docc": float(np.trace(corr[2])), "norm2": float(norm)}
+
+    def propagate(self, psi0: np.ndarray, t: float) -> np.ndarray:
+        """exp(-i H t) psi0 for a complex psi0 (the time evolution that the
+        product H.v also drives), written out as its definition: H = V diag(w) V^T
+        from the dense symmetric eigenproblem (numpy.linalg.eigh), then
+        V diag(exp(-i w t)) V^T psi0.  Small sectors only."""
+        psi0 = np.asarray(psi0, dtype=np.complex128)
+        assert psi0.shape == (self.dim,)
+        w, V = np.linalg.eigh(self.dense())
+        return V @ (np.exp(-1j * w * t) * (V.T @ psi0))
 
     def lanczos(self, f1: np.ndarray, tol: float = 1e-12, max_iter: int = 300, want_psi: bool = False):
         """Alg. 1 from the unit start vector f1; returns a dict with a_j, b_{j+1},

@@ -464,3 +464,45 @@ def test_observable_sum_rules():
     assert np.allclose(o["corr"][2].sum(axis=0), nu * o["dens"][1], atol=1e-12)
     o2 = m.observables(3.0 * v)
     assert np.allclose(o2["corr"], o["corr"], atol=1e-14) and o2["docc"] == pytest.approx(o["docc"], abs=1e-14)
+
+
+# ------------------------------------------------------------------ time evolution exp(-i H t)
+
+def test_propagate_single_particle_ring_closed_form():
+    """One up electron on an L-site ring, U irrelevant: starting on site 0 the amplitude
+    on site j at time T is (1/L) sum_k exp(i k j) exp(2 i t T cos k), k = 2 pi n / L."""
+    L, t, T = 7, 0.9, 1.7
+    m = oracle.Model(L, workload.ring(L), 1, 0, t, 5.0)
+    states = oracle.basis(L, 1)
+    psi0 = np.zeros(m.dim, dtype=complex)
+    psi0[oracle.position(states, 1)] = 1.0
+    got = m.propagate(psi0, T)
+    for j in range(L):
+        ref = sum(np.exp(1j * k * j) * np.exp(2j * t * T * math.cos(k))
+                  for k in (2 * math.pi * n / L for n in range(L))) / L
+        assert abs(got[oracle.position(states, 1 << j)] - ref) < 1e-12
+
+
+def test_propagate_atomic_limit_phases():
+    """t = 0: each configuration only picks up the phase exp(-i U d_J T), d_J its
+    number of doubly occupied sites."""
+    ns, nu, nd, U, T = 5, 3, 2, 1.3, 2.2
+    m = oracle.Model(ns, workload.ring(ns), nu, nd, 0.0, U)
+    d = m.diagonal() / U
+    psi0 = RNG.uniform(-1, 1, m.dim) + 1j * RNG.uniform(-1, 1, m.dim)
+    assert np.allclose(m.propagate(psi0, T), np.exp(-1j * U * d * T) * psi0, atol=1e-13)
+
+
+def test_propagate_eigenstate_phase_group_and_unitarity():
+    """An eigenvector only gains exp(-i E T); exp(-iH a) exp(-iH b) = exp(-iH (a+b));
+    the norm and <H> are conserved; T = 0 is the identity."""
+    m = oracle.Model(6, workload.torus(2, 3), 3, 3, 1.0, 3.0)
+    w, V = m.lowest_states(1)
+    assert np.allclose(m.propagate(V[0], 0.8), np.exp(-0.8j * w[0]) * V[0], atol=1e-12)
+    psi0 = RNG.uniform(-1, 1, m.dim) + 1j * RNG.uniform(-1, 1, m.dim)
+    a = m.propagate(m.propagate(psi0, 0.3), 0.45)
+    assert np.allclose(a, m.propagate(psi0, 0.75), atol=1e-12)
+    assert np.linalg.norm(a) == pytest.approx(np.linalg.norm(psi0), rel=1e-13)
+    e = lambda v: (np.vdot(v, m.apply(v.real) + 1j * m.apply(v.imag)) / np.vdot(v, v)).real
+    assert e(a) == pytest.approx(e(psi0), rel=1e-12)
+    assert np.allclose(m.propagate(psi0, 0.0), psi0, atol=1e-14)
