@@ -18,6 +18,7 @@ Printed JSON line (one):
   cpu_baseline   the sequential FP64 oracle on one host core, bounded sample
   excited        the k lowest states of the same sector (hubbard_lowest_states) and
                  the site observables of its ground state (hubbard_observables)
+  propagation    exp(-iHt) psi on the same sector (hubbard_propagate, resident Krylov basis)
 
 Other modes:
   --calibrate-copy           also run one device copy of known size (for counter scaling)
@@ -283,6 +284,55 @@ def oracle_excited_check():
     return out
 
 
+def bench_propagate(hb, torch, p, T, n_steps, m):
+    """exp(-i H T) psi through hubbard_propagate from a seeded complex start
+    (real and imaginary parts from the library's SplitMix64 start vector with
+    seeds seed and seed + 1, normalised together); the Krylov basis of m + 1
+    complex vectors stays on the device."""
+    h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    re = torch.empty(p.dim, dtype=torch.float64, device="cuda:0")
+    im = torch.empty_like(re)
+    hb.hubbard_start_raw(p.seed, p.dim, re)
+    hb.hubbard_start_raw(p.seed + 1, p.dim, im)
+    nrm = float(torch.sqrt(torch.dot(re, re) + torch.dot(im, im)))
+    re /= nrm
+    im /= nrm
+    if p.dim <= 6000:
+        bench_propagate.start[p.name] = (p, re.cpu().numpy() + 1j * im.cpu().numpy(), T)
+    torch.cuda.synchronize()
+    r = hb.hubbard_propagate(h, re, im, T, n_steps, m)
+    if p.dim <= 6000:
+        bench_propagate.result[p.name] = re.cpu().numpy() + 1j * im.cpu().numpy()
+    e = r["energy"]
+    ld = hb.hubbard_info(h)["ld_pref"]
+    return {"workload": p.name, "dim": p.dim, "t": T, "n_steps": n_steps, "krylov_dim": m,
+            "seconds": round(r["seconds"], 4),
+            "ms_per_krylov_step": round(r["seconds"] / (n_steps * m) * 1e3, 3),
+            "basis_GB": round(16 * (m + 1) * h.dim_up * ld / 1e9, 2),
+            "err_est": float("%.3g" % r["err_est"]), "norm_drift": float("%.3g" % abs(r["norm"] - 1.0)),
+            "energy": float(e[0]), "energy_drift": float("%.3g" % float(max(abs(x - e[0]) for x in e)))}
+
+
+bench_propagate.start = {}
+bench_propagate.result = {}
+
+
+def oracle_propagate_check():
+    """The oracle's dense exp(-i H T) on the same start vector (timed) against
+    the GPU's result, for the sectors it can reach."""
+    import numpy as np
+    import oracle
+    out = {}
+    for name, (p, psi0, T) in bench_propagate.start.items():
+        m = oracle.Model(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+        t0 = time.perf_counter()
+        ref = m.propagate(psi0, T)
+        dt = time.perf_counter() - t0
+        out[name] = {"oracle_seconds": round(dt, 3),
+                     "max_abs_err_vs_oracle": float("%.3g" % np.abs(bench_propagate.result[name] - ref).max())}
+    return out
+
+
 def golden(name):
     """A stored oracle run (written by tests/golden/make_oracle_golden.py)."""
     path = os.path.join(ROOT, "tests", "golden", name)
@@ -439,6 +489,7 @@ def _kernel_family(name):
                 "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel",
                 "axpy_norm_kernel", "defl_dots_kernel", "defl_update_kernel", "obs_accumulate_kernel",
                 "obs_sum_groups_kernel", "obs_sum_kernel", "psi_stats_kernel", "scale_kernel",
+                "prop_load_kernel", "prop_update_kernel", "prop_combine_kernel", "prop_reduce_kernel",
                 "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
                 "psi_acc_kernel", "copyBuffer", "elementwise"):
         if fam in name:
@@ -535,6 +586,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="solves in the batch leg (0 skips it)")
     ap.add_argument("--serve", type=int, default=200, help="requests in the serving leg (0 skips it)")
     ap.add_argument("--no-small", action="store_true", help="skip the 14-site and 8-site ring legs")
+    ap.add_argument("--propagate", type=int, default=1, help="real-time propagation leg (0 skips it)")
     ap.add_argument("--excited", type=int, default=3,
                     help="lowest states in the excited-state leg on the 4x4 lattice (0 skips it)")
     ap.add_argument("--summarize-trace")
@@ -628,6 +680,12 @@ def main():
             ex["ring8"] = bench_excited(hb, torch, workload.problem("ring8_3u3d_U4", 8, workload.ring(8), 3, 3,
                                                                     1.0, 4.0), 6, EXCITED_TOL["ring8"])
         out["excited"] = ex
+    if args.propagate:
+        log("propagation leg: exp(-iHt) on", p.name)
+        pr = {"square4x4": bench_propagate(hb, torch, p, 0.1, 2, 16)}
+        if not args.no_small:
+            pr["ring8"] = bench_propagate(hb, torch, workload.ring8(), 1.0, 10, 16)
+        out["propagation"] = pr
     batch_probs = None
     if args.batch:
         log("batch leg:", args.batch, "solves")
@@ -647,6 +705,9 @@ def main():
             cs = oracle_serving_check(bench_serving.results)
             if cs is not None:
                 cb["serving"] = cs
+        if bench_propagate.start:
+            log("oracle beside the propagation leg")
+            cb["propagation"] = oracle_propagate_check()
         if bench_excited.vectors:
             log("oracle beside the excited-state leg")
             cb["excited"] = oracle_excited_check()

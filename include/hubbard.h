@@ -210,6 +210,37 @@ int hubbard_lowest_states(hubbard_h h, int k, const hubbard_opts *opts, double *
  * Synchronous on the handle's stream. */
 int hubbard_observables(hubbard_h h, const double *psi, double *dens, double *corr, double *docc);
 
+/* Result of hubbard_propagate. */
+typedef struct {
+    double err_est;          /* sum over the steps of |psi| b_{m+1} |(exp(-i T_m dt) e_1)_m|: the Lanczos
+                                estimate of each step's error (0 for a step that ended in an invariant subspace) */
+    double norm;             /* |psi| after the last step (the start norm, up to that error) */
+    double seconds;          /* wall time of the call */
+    int32_t n_steps;
+    int32_t krylov_dim_max;  /* largest Krylov dimension a step used (smaller after an invariant subspace) */
+} hubbard_prop_result;
+
+/* Real-time evolution psi <- exp(-i H t) psi (H of eq. H; the H.v of Sec. 4.3
+ * drives it as it drives the ground-state search) in n_steps equal steps of
+ * dt = t / n_steps.  Each step runs the recurrence of Alg. 1 on the complex
+ * vector for krylov_dim steps (H is real and symmetric, so the coefficients
+ * are real), keeps the whole Krylov basis on the device, and forms
+ * psi(t + dt) = |psi| V_m exp(-i T_m dt) e_1 from it; a vanishing b_{j+1}
+ * (an invariant subspace) makes the step exact with the smaller basis.
+ * Always FP64, whatever the handle's precision.
+ *   psi_re, psi_im: device FP64 arrays of dim elements (J order), the real and
+ *     imaginary parts, overwritten with the result; distinct, non-overlapping.
+ *   t: finite (negative t runs backwards).  n_steps >= 1.  krylov_dim: 2..64.
+ *   energy: NULL or host array[n_steps + 1] receiving <psi|H|psi>/<psi|psi> at
+ *     t_k = k dt, k = 0..n_steps (conserved by the exact evolution).
+ *   res: NULL or a host result record.
+ * Device memory: (krylov_dim + 1) complex vectors in the padded row layout
+ * (16 (krylov_dim + 1) dim_up ld_pref bytes) for the duration of the call.
+ * Errors: EINVAL (bad argument, or psi of zero norm), ENOMEM, EDEVICE.
+ * Synchronous on the handle's stream. */
+int hubbard_propagate(hubbard_h h, double *psi_re, double *psi_im, double t, int n_steps, int krylov_dim,
+                      double *energy, hubbard_prop_result *res);
+
 /* Sizes of the handle's sector and tables. */
 int hubbard_info(hubbard_h h, hubbard_info_t *info);
 

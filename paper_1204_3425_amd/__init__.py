@@ -67,6 +67,11 @@ class hubbard_result(ctypes.Structure):
                 ("precision", ctypes.c_int32)]
 
 
+class hubbard_prop_result(ctypes.Structure):
+    _fields_ = [("err_est", ctypes.c_double), ("norm", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("n_steps", ctypes.c_int32), ("krylov_dim_max", ctypes.c_int32)]
+
+
 class hubbard_request(ctypes.Structure):
     _fields_ = [("sites", ctypes.c_int32), ("edges", ctypes.c_void_p), ("n_edges", ctypes.c_int32),
                 ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_double),
@@ -117,6 +122,7 @@ def _load():
         "hubbard_lanczos_batch": [vp, i32, ctypes.POINTER(hubbard_opts), ctypes.POINTER(hubbard_result)],
         "hubbard_lowest_states": [vp, i32, ctypes.POINTER(hubbard_opts), vp, vp, ctypes.POINTER(hubbard_result)],
         "hubbard_observables": [vp, vp, vp, vp, vp],
+        "hubbard_propagate": [vp, vp, vp, dbl, i32, i32, vp, ctypes.POINTER(hubbard_prop_result)],
         "hubbard_server_create": [ctypes.c_size_t, i32, ctypes.POINTER(vp)],
         "hubbard_server_submit": [vp, ctypes.POINTER(hubbard_request), ctypes.POINTER(ctypes.c_uint64)],
         "hubbard_server_poll": [vp, ctypes.POINTER(hubbard_completion), i32, ctypes.POINTER(ctypes.c_int), i32],
@@ -360,6 +366,22 @@ def hubbard_observables(h: Handle, psi, stream="current") -> dict:
     _check(_lib.hubbard_observables(h, _dev_ptr(psi, "float64", h.dim, "psi"), dens.ctypes.data, corr.ctypes.data,
                                     ctypes.byref(d)), "hubbard_observables")
     return {"dens": dens.reshape(2, n), "corr": corr.reshape(3, n, n), "docc": d.value}
+
+
+def hubbard_propagate(h: Handle, psi_re, psi_im, t: float, n_steps: int = 1, krylov_dim: int = 20,
+                      stream="current") -> dict:
+    """psi <- exp(-i H t) psi in place (device FP64 tensors of dim elements for the
+    real and imaginary parts); returns the energy at every step boundary and the
+    result record as a dict."""
+    if stream == "current":
+        hubbard_set_stream(h, _current_stream())
+    energy = np.zeros(max(int(n_steps), 0) + 1)
+    r = hubbard_prop_result()
+    _check(_lib.hubbard_propagate(h, _dev_ptr(psi_re, "float64", h.dim, "psi_re"),
+                                  _dev_ptr(psi_im, "float64", h.dim, "psi_im"), float(t), int(n_steps),
+                                  int(krylov_dim), energy.ctypes.data, ctypes.byref(r)), "hubbard_propagate")
+    return {"energy": energy, "err_est": r.err_est, "norm": r.norm, "seconds": r.seconds, "n_steps": r.n_steps,
+            "krylov_dim_max": r.krylov_dim_max}
 
 
 def hubbard_info(h: Handle) -> dict:

@@ -14,7 +14,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
 SOURCES = ["builder.cpp", "tridiag.cpp", "capi.cpp", "kernels.hip", "hv.hip", "batch.hip", "batch.cpp", "server.cpp",
-           "observables.hip"]
+           "observables.hip", "propagate.hip"]
 
 
 def build(verbose: bool = False) -> str:

@@ -665,6 +665,110 @@ int lowest_states_impl(hubbard *h, int k, const hubbard_opts &o, double *E, doub
     return worst;
 }
 
+// Krylov dimension limit of one propagation step
+constexpr int kMaxKrylov = 64;
+
+int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, int m, double *energy,
+                   hubbard_prop_result *res)
+{
+    if (!re || !im || re == im)
+        fail(HUBBARD_EINVAL, "psi_re and psi_im must be two distinct device arrays");
+    if (!std::isfinite(t))
+        fail(HUBBARD_EINVAL, "t is not finite");
+    if (n_steps < 1)
+        fail(HUBBARD_EINVAL, "n_steps must be >= 1");
+    if (m < 2 || m > kMaxKrylov)
+        fail(HUBBARD_EINVAL, "krylov_dim must lie in 2.." + std::to_string(kMaxKrylov));
+    use_device(h);
+    auto t0 = std::chrono::steady_clock::now();
+    const HvArgs args = hv_args(h);
+    hipStream_t s = h->stream;
+    const HvPlan plan = make_hv_plan(args, sizeof(double));
+    const int64_t ld = plan.ld, npad = h->up.dim * ld, stride = 2 * npad;
+    const int64_t du = h->up.dim, dd = h->dn.dim;
+    // the Krylov basis, resident: slot m receives the last H.v of a step.  The
+    // H.v runs with beta = 0 on the old contents of a slot, so they start as zeros.
+    const size_t bbytes = sizeof(double) * (size_t)stride * (size_t)(m + 1);
+    DevBuf basis(bbytes);
+    HUB_HIP(hipMemsetAsync(basis.p, 0, bbytes, s));
+    DevBuf partials(sizeof(double) * (size_t)(std::max(2 * plan.nparts, 4096) + 64));
+    DevBuf scal(sizeof(double) * 4 * (size_t)(m + 2));
+    DevBuf gamd(sizeof(double) * 2 * (size_t)m);
+    PinnedBuf host(sizeof(double) * (4 * (size_t)(m + 2) + 2 * (size_t)m));
+    double *sh = host.as<double>(), *gh = sh + 4 * (m + 2);
+    double *sc = scal.as<double>(), *B = basis.as<double>(), *part = partials.as<double>();
+    auto slot = [&](int j) { return B + (size_t)j * (size_t)stride; };
+
+    int nb = launch_prop_load(re, im, B, npad, du, dd, ld, part, s);
+    launch_prop_reduce(part, nb, PROP_START, sc, 0, s);
+    const double dt = t / n_steps;
+    double err = 0.0;
+    int mmax = 0;
+    for (int k = 0; k <= n_steps; k++) {
+        // the round after the last step only measures <H> of the final state
+        const int msteps = k < n_steps ? m : 1;
+        for (int j = 0; j < msteps; j++) {
+            const int np = launch_hv2<double>(args, plan, slot(j), ld, slot(j + 1), ld, nullptr, 0, HV_LANCZOS, 0.0,
+                                              sc + 4 * j, part, s);
+            const int np2 = launch_hv2<double>(args, plan, slot(j) + npad, ld, slot(j + 1) + npad, ld, nullptr, 0,
+                                               HV_LANCZOS, 0.0, sc + 4 * j, part + np, s);
+            launch_prop_reduce(part, np + np2, PROP_DOT, sc, j, s);
+            if (k == n_steps)
+                break;
+            nb = launch_prop_update(slot(j + 1), slot(j), j > 0 ? slot(j - 1) : nullptr, sc, j, stride, part, s);
+            launch_prop_reduce(part, nb, PROP_NORM, sc, j, s);
+        }
+        HUB_HIP(hipMemcpyAsync(sh, sc, sizeof(double) * 4 * (size_t)(msteps + 1), hipMemcpyDeviceToHost, s));
+        HUB_HIP(hipStreamSynchronize(s));
+        if (!(sh[0] > 0.0) || !std::isfinite(sh[0]))
+            fail(k == 0 ? HUBBARD_EINVAL : HUBBARD_EDEVICE, "psi has zero or non-finite norm");
+        if (energy)
+            energy[k] = sh[2];
+        if (k == n_steps)
+            break;
+        // Krylov dimension: up to the first vanishing b_{j+1} (an invariant subspace, where the step is exact)
+        int nv = m;
+        double scale = 0.0;
+        for (int j = 0; j < m; j++) {
+            const double a = sh[4 * j + 2], b = sh[4 * j + 3];
+            if (!std::isfinite(a) || !std::isfinite(b))
+                fail(HUBBARD_EDEVICE, "non-finite Krylov coefficient in step " + std::to_string(k + 1));
+            scale = std::fmax(scale, std::fabs(a) + (j > 0 ? sh[4 * (j - 1) + 3] : 0.0));
+            if (!(b > 1e-12 * scale)) {
+                nv = j + 1;
+                break;
+            }
+        }
+        std::vector<double> d((size_t)nv), e((size_t)nv), cr((size_t)nv), ci((size_t)nv);
+        for (int j = 0; j < nv; j++) {
+            d[(size_t)j] = sh[4 * j + 2];
+            e[(size_t)j] = sh[4 * j + 3];
+        }
+        tridiag_expm_e1(d.data(), e.data(), nv, dt, cr.data(), ci.data());
+        const double nrm = 1.0 / sh[0];  // |psi| at the start of the step
+        if (nv == m)
+            err += nrm * sh[4 * (m - 1) + 3] * std::hypot(cr[(size_t)m - 1], ci[(size_t)m - 1]);
+        for (int j = 0; j < nv; j++) {
+            gh[2 * j] = nrm * cr[(size_t)j] * sh[4 * j];
+            gh[2 * j + 1] = nrm * ci[(size_t)j] * sh[4 * j];
+        }
+        HUB_HIP(hipMemcpyAsync(gamd.p, gh, sizeof(double) * 2 * (size_t)nv, hipMemcpyHostToDevice, s));
+        nb = launch_prop_combine(B, nv, stride, npad, gamd.as<double>(), re, im, du, dd, ld, part, s);
+        launch_prop_reduce(part, nb, PROP_START, sc, 0, s);
+        mmax = std::max(mmax, nv);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        res->err_est = err;
+        res->norm = 1.0 / sh[0];
+        res->seconds = std::chrono::duration<double>(t1 - t0).count();
+        res->n_steps = n_steps;
+        res->krylov_dim_max = mmax;
+    }
+    return HUBBARD_OK;
+}
+
 }  // namespace hub
 
 using namespace hub;
@@ -903,6 +1007,15 @@ int hubbard_observables(hubbard_h h, const double *psi, double *dens, double *co
             *docc = d / norm;
         }
         return HUBBARD_OK;
+    });
+}
+
+int hubbard_propagate(hubbard_h h, double *psi_re, double *psi_im, double t, int n_steps, int krylov_dim,
+                      double *energy, hubbard_prop_result *res)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        return propagate_impl(h, psi_re, psi_im, t, n_steps, krylov_dim, energy, res);
     });
 }
 

@@ -95,6 +95,8 @@ uint64_t binomial(int n, int k);
 // off-diagonal e[i] between rows i and i+1 (i < m-1).
 double tridiag_lowest(const double *d, const double *e, int m);
 void tridiag_lowest_vector(const double *d, const double *e, int m, double lam, double *y);
+// c = exp(-i tau T) e_1 (real and imaginary parts, m each); e holds the m-1 off-diagonals
+void tridiag_expm_e1(const double *d, const double *e, int m, double tau, double *c_re, double *c_im);
 
 // kernels.hip: launchers (all asynchronous on `s`).
 struct HvArgs {
@@ -178,6 +180,17 @@ int obs_ns_max(int sites);
 int obs_partial_count(int ns, int64_t dim_up, int64_t dim_dn);
 void launch_observables(const double *psi, const uint32_t *states_up, const uint32_t *states_dn, int ns,
                         int64_t dim_up, int64_t dim_dn, double *part, double *out, hipStream_t s);
+
+// propagate.hip: the Krylov propagation step (see the file's header for the
+// slot layout and the device scalars sc[4j..4j+3] = {s_j, 0, a_j, b_{j+1}})
+enum PropMode { PROP_START = 0, PROP_DOT = 1, PROP_NORM = 2 };
+int launch_prop_load(const double *re, const double *im, double *slot, int64_t npad, int64_t dim_up, int64_t dim_dn,
+                     int64_t ld, double *partials, hipStream_t s);
+int launch_prop_update(double *y, const double *w, const double *wp, const double *sc, int j, int64_t n,
+                       double *partials, hipStream_t s);
+int launch_prop_combine(double *basis, int nv, int64_t slot_stride, int64_t npad, const double *gam, double *re,
+                        double *im, int64_t dim_up, int64_t dim_dn, int64_t ld, double *partials, hipStream_t s);
+void launch_prop_reduce(const double *partials, int n, int mode, double *sc, int j, hipStream_t s);
 
 // Most lower eigenvectors one deflated Lanczos run projects out.
 constexpr int kMaxDeflate = 15;

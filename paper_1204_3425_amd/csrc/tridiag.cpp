@@ -137,3 +137,74 @@ void tridiag_lowest_vector(const double *d, const double *e, int m, double lam, 
 }
 
 }  // namespace hub
+
+namespace hub {
+
+// c = exp(-i tau T) e_1 for the symmetric tridiagonal T (diagonal d[0..m-1],
+// off-diagonal e[0..m-2]): T = Z diag(w) Z^T by cyclic Jacobi rotations on the
+// dense m x m matrix (Golub and Van Loan, Matrix Computations, the cyclic
+// Jacobi method), then c = Z diag(exp(-i tau w)) Z^T e_1.  m is small (the
+// Krylov dimension of one propagation step), so O(m^3) per sweep is nothing.
+void tridiag_expm_e1(const double *d, const double *e, int m, double tau, double *c_re, double *c_im)
+{
+    std::vector<double> A((size_t)m * m, 0.0), Z((size_t)m * m, 0.0);
+    for (int i = 0; i < m; i++) {
+        A[(size_t)i * m + i] = d[i];
+        Z[(size_t)i * m + i] = 1.0;
+        if (i + 1 < m) {
+            A[(size_t)i * m + i + 1] = e[i];
+            A[(size_t)(i + 1) * m + i] = e[i];
+        }
+    }
+    double fro = 0.0;
+    for (double v : A)
+        fro += v * v;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = 0.0;
+        for (int p = 0; p < m; p++)
+            for (int q = p + 1; q < m; q++)
+                off += A[(size_t)p * m + q] * A[(size_t)p * m + q];
+        if (off <= 1e-34 * fro || off == 0.0)
+            break;
+        for (int p = 0; p < m; p++)
+            for (int q = p + 1; q < m; q++) {
+                const double apq = A[(size_t)p * m + q];
+                if (apq == 0.0)
+                    continue;
+                const double theta = (A[(size_t)q * m + q] - A[(size_t)p * m + p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(1.0 + theta * theta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                // A <- J^T A J with J the rotation in the (p, q) plane
+                for (int k = 0; k < m; k++) {
+                    const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                    A[(size_t)k * m + p] = c * akp - s * akq;
+                    A[(size_t)k * m + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < m; k++) {
+                    const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+                    A[(size_t)p * m + k] = c * apk - s * aqk;
+                    A[(size_t)q * m + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < m; k++) {
+                    const double zkp = Z[(size_t)k * m + p], zkq = Z[(size_t)k * m + q];
+                    Z[(size_t)k * m + p] = c * zkp - s * zkq;
+                    Z[(size_t)k * m + q] = s * zkp + c * zkq;
+                }
+            }
+    }
+    for (int i = 0; i < m; i++) {
+        c_re[i] = 0.0;
+        c_im[i] = 0.0;
+    }
+    for (int k = 0; k < m; k++) {
+        const double w = A[(size_t)k * m + k];
+        const double z0 = Z[k];  // Z[0][k]
+        const double pr = std::cos(tau * w) * z0, pi = -std::sin(tau * w) * z0;
+        for (int i = 0; i < m; i++) {
+            c_re[i] += Z[(size_t)i * m + k] * pr;
+            c_im[i] += Z[(size_t)i * m + k] * pi;
+        }
+    }
+}
+
+}  // namespace hub
