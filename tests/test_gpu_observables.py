@@ -49,7 +49,7 @@ CASES = [
     ("torus4x4_2u5d", 16, workload.torus(4, 4), 2, 5),
     # more than 16 sites: the 32-site variant of the kernel
     ("ring20_1u2d", 20, workload.ring(20), 1, 2),
-    ("ring32_1u1d", 32, workload.ring(32), 1, 1),
+    ("ring24_1u2d", 24, workload.ring(24), 1, 2),
 ]
 
 
