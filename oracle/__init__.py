@@ -58,6 +58,9 @@ def lib():
             L.orc_model_new.restype = _p
             L.orc_model_new.argtypes = [ctypes.c_int, _p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double]
+            L.orc_model_new_bonds.restype = _p
+            L.orc_model_new_bonds.argtypes = [ctypes.c_int, _p, _p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_double]
             L.orc_model_free.argtypes = [_p]
             L.orc_dim.restype = _i64
             L.orc_dim.argtypes = [_p, ctypes.c_int]
@@ -143,10 +146,19 @@ class Model:
     """
 
     def __init__(self, ns, edges, n_up, n_dn, t=1.0, U=0.0):
+        """t: one amplitude for every bond (eq. H), or a sequence with one
+        amplitude per bond (the hop over bond k then has element -t[k] * sign)."""
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         self._edges = e
-        self.ns, self.n_up, self.n_dn, self.t, self.U = ns, n_up, n_dn, float(t), float(U)
-        self._h = lib().orc_model_new(ns, _ptr(e), len(e), n_up, n_dn, self.t, self.U)
+        self.ns, self.n_up, self.n_dn, self.U = ns, n_up, n_dn, float(U)
+        if np.ndim(t) == 0:
+            self.t = float(t)
+            self._h = lib().orc_model_new(ns, _ptr(e), len(e), n_up, n_dn, self.t, self.U)
+        else:
+            amp = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+            assert amp.shape == (len(e),)
+            self.t = amp.copy()
+            self._h = lib().orc_model_new_bonds(ns, _ptr(e), _ptr(amp), len(e), n_up, n_dn, self.U)
         if not self._h:
             raise MemoryError("oracle model allocation failed")
         self.dim_up = int(lib().orc_dim(self._h, 0))

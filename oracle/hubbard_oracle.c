@@ -114,7 +114,7 @@ static int cmp_entry(const void *pa, const void *pb)
     return (a[0] > b[0]) - (a[0] < b[0]);
 }
 
-static int build_spin_table(spin_table *tb, int ns, const int32_t *edges, int ne, int n, double t)
+static int build_spin_table(spin_table *tb, int ns, const int32_t *edges, const double *amp, int ne, int n)
 {
     int64_t dim = orc_basis(ns, n, NULL, 0);
     tb->dim = dim;
@@ -154,7 +154,7 @@ static int build_spin_table(spin_table *tb, int ns, const int32_t *edges, int ne
                     uint32_t s2 = s - (1u << from) + (1u << to);
                     int64_t c = orc_position(tb->states, dim, s2);
                     int nb = count_between(s, from, to);
-                    double v = -t * ((nb % 2) ? -1.0 : 1.0);
+                    double v = -amp[e] * ((nb % 2) ? -1.0 : 1.0);
                     tmp[2 * m] = c;
                     memcpy(&tmp[2 * m + 1], &v, sizeof(double));
                     m++;
@@ -190,21 +190,37 @@ typedef struct {
     int64_t dim;
 } orc_model;
 
-orc_model *orc_model_new(int ns, const int32_t *edges, int ne, int n_up, int n_dn, double t, double U)
+/* The model with one hopping amplitude per bond: the hop over edge e has the
+ * element -amp[e] * (-1)^n (eq. H with t_ij for t; Sec. 2.1 notes that the
+ * construction holds for any lattice).  amp[e] = t for every e is the model of
+ * eq. H itself. */
+orc_model *orc_model_new_bonds(int ns, const int32_t *edges, const double *amp, int ne, int n_up, int n_dn, double U)
 {
     orc_model *m = (orc_model *)calloc(1, sizeof(orc_model));
     if (!m)
         return NULL;
     m->ns = ns;
-    m->t = t;
+    m->t = ne > 0 ? amp[0] : 0.0;
     m->U = U;
-    if (build_spin_table(&m->up, ns, edges, ne, n_up, t) || build_spin_table(&m->dn, ns, edges, ne, n_dn, t)) {
+    if (build_spin_table(&m->up, ns, edges, amp, ne, n_up) || build_spin_table(&m->dn, ns, edges, amp, ne, n_dn)) {
         free_spin_table(&m->up);
         free_spin_table(&m->dn);
         free(m);
         return NULL;
     }
     m->dim = m->up.dim * m->dn.dim;
+    return m;
+}
+
+orc_model *orc_model_new(int ns, const int32_t *edges, int ne, int n_up, int n_dn, double t, double U)
+{
+    double *amp = (double *)malloc(sizeof(double) * (size_t)(ne > 0 ? ne : 1));
+    if (!amp)
+        return NULL;
+    for (int e = 0; e < ne; e++)
+        amp[e] = t;
+    orc_model *m = orc_model_new_bonds(ns, edges, amp, ne, n_up, n_dn, U);
+    free(amp);
     return m;
 }
 

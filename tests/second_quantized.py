@@ -47,6 +47,8 @@ def _hop(ops, spin, a, b):
 
 
 def dense_hamiltonian(ns, edges, n_up, n_dn, t, U):
+    """t: one amplitude for all bonds, or one per bond (in the order of edges)."""
+    amps = [t] * len(edges) if np.ndim(t) == 0 else list(t)
     ups, dns = _configs(ns, n_up), _configs(ns, n_dn)
     iu = {w: k for k, w in enumerate(ups)}
     idn = {w: k for k, w in enumerate(dns)}
@@ -59,7 +61,7 @@ def dense_hamiltonian(ns, edges, n_up, n_dn, t, U):
             # interaction: U n_{i up} n_{i dn}
             H[J, J] += U * sum(1 for s in range(ns) if (0, s) in ops and (1, s) in ops)
             # hopping: -t sum_<ij> sum_s (c^dag_i c_j + c^dag_j c_i)
-            for (i, j) in edges:
+            for (i, j), tb in zip(edges, amps):
                 for spin in (0, 1):
                     for (a, b) in ((i, j), (j, i)):
                         r = _hop(ops, spin, a, b)
@@ -69,5 +71,5 @@ def dense_hamiltonian(ns, edges, n_up, n_dn, t, U):
                         nu = sum(1 << s for (sp, s) in new if sp == 0)
                         nd = sum(1 << s for (sp, s) in new if sp == 1)
                         J2 = iu[nu] * len(dns) + idn[nd]
-                        H[J2, J] += -t * sign
+                        H[J2, J] += -tb * sign
     return H

@@ -506,3 +506,51 @@ def test_propagate_eigenstate_phase_group_and_unitarity():
     e = lambda v: (np.vdot(v, m.apply(v.real) + 1j * m.apply(v.imag)) / np.vdot(v, v)).real
     assert e(a) == pytest.approx(e(psi0), rel=1e-12)
     assert np.allclose(m.propagate(psi0, 0.0), psi0, atol=1e-14)
+
+
+# ------------------------------------------------------------------ per-bond amplitudes t_ij
+
+@pytest.mark.parametrize("name,ns,edges", SMALL_LATTICES[2:])
+def test_bond_amplitudes_match_second_quantized(name, ns, edges):
+    """eq. H with t_ij in place of t (Sec. 2.1: any lattice): the oracle's H equals
+    the operator-by-operator brute force for random per-bond amplitudes."""
+    g = np.random.default_rng(len(edges) * 31 + ns)
+    amps = g.uniform(-2, 2, len(edges))
+    for nu, nd in [(1, 1), (2, 1), (ns // 2, (ns + 1) // 2)]:
+        if math.comb(ns, nu) * math.comb(ns, nd) > 400:
+            continue
+        ref = dense_hamiltonian(ns, edges, nu, nd, amps, 1.7)
+        got = oracle.Model(ns, edges, nu, nd, amps, 1.7).dense()
+        assert np.allclose(got, ref, rtol=0, atol=1e-15), (name, nu, nd)
+
+
+def test_bond_amplitudes_uniform_is_the_scalar_model():
+    m1 = oracle.Model(6, workload.torus(2, 3), 3, 2, 1.3, 4.0)
+    m2 = oracle.Model(6, workload.torus(2, 3), 3, 2, [1.3] * len(workload.torus(2, 3)), 4.0)
+    assert np.array_equal(m1.dense(), m2.dense())
+
+
+def test_bond_amplitudes_ssh_single_particle_band():
+    """One electron on an even ring with alternating amplitudes t1, t2 (two-site
+    unit cell): levels +-|t1 + t2 exp(i q)|, q = 2 pi n / (L/2)."""
+    L, t1, t2 = 10, 1.0, 0.45
+    edges = workload.ring(L)
+    amps = [t1 if (min(i, j) % 2 == 0 and abs(i - j) == 1) else t2 for (i, j) in edges]
+    # the wrap bond (0, L-1) joins cells: it carries t2
+    m = oracle.Model(L, edges, 1, 0, amps, 3.0)
+    w = np.linalg.eigvalsh(m.dense())
+    qs = [2 * math.pi * n / (L // 2) for n in range(L // 2)]
+    ref = np.sort([s * abs(t1 + t2 * np.exp(1j * q)) for q in qs for s in (1, -1)])
+    assert np.allclose(w, ref, atol=1e-12)
+
+
+def test_bond_amplitude_sign_gauge():
+    """Flipping the sign of every bond leaving one sublattice site of a bipartite
+    lattice is a gauge transformation (c_i -> -c_i on that site): the spectrum stays."""
+    ns, edges = 8, workload.ring(8)
+    g = np.random.default_rng(5)
+    amps = g.uniform(0.5, 1.5, len(edges))
+    flip = np.array([-a if 3 in e else a for a, e in zip(amps, edges)])
+    w1 = np.linalg.eigvalsh(oracle.Model(ns, edges, 2, 2, amps, 2.0).dense())
+    w2 = np.linalg.eigvalsh(oracle.Model(ns, edges, 2, 2, flip, 2.0).dense())
+    assert np.allclose(w1, w2, atol=1e-11)
