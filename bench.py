@@ -19,6 +19,7 @@ Printed JSON line (one):
   excited        the k lowest states of the same sector (hubbard_lowest_states) and
                  the site observables of its ground state (hubbard_observables)
   propagation    exp(-iHt) psi on the same sector (hubbard_propagate, resident Krylov basis)
+  bonds          per-bond amplitudes t_ij (hubbard_build_bonds): 4x4 t-t' H.v, 3x4 t-t' solve
 
 Other modes:
   --calibrate-copy           also run one device copy of known size (for counter scaling)
@@ -333,6 +334,41 @@ def oracle_propagate_check():
     return out
 
 
+def bench_bonds(hb, torch):
+    """Per-bond amplitudes (hubbard_build_bonds, the one-pass H.v): the 4x4
+    lattice with nearest-neighbour t = 1 and diagonal t' = -0.3 (U = 8, 8 up +
+    8 down) for the H.v rate, and the 3x4 lattice with the same amplitudes
+    (4 up + 4 down, dim 245,025) for a solve the oracle repeats."""
+    import workload
+    edges, amps = workload.torus_tprime(4, 4, 1.0, -0.3)
+    h = hb.hubbard_build_bonds(16, edges, amps, 8, 8, 8.0)
+    t64 = time_hv(hb, torch, h, hb.HUBBARD_FP64, 5, 1, median=True)
+    dim = h.dim
+    del h
+    e2, a2 = workload.torus_tprime(3, 4, 1.0, -0.3)
+    h2 = hb.hubbard_build_bonds(12, e2, a2, 4, 4, 8.0)
+    r = hb.hubbard_lanczos_ex(h2, tol=1e-12, max_iter=400, precision=hb.HUBBARD_FP64, seed=12043425)
+    bench_bonds.solve = (e2, a2, r["E0"])
+    return {"square4x4_tprime": {"bonds": len(edges), "dim": dim, "hv_fp64_us": round(t64 * 1e6, 1),
+                                 "hv_fp64_gbs": round(2 * dim * 8 / t64 / 1e9, 1)},
+            "torus3x4_tprime_4u4d": {"dim": h2.dim, "E0": r["E0"], "iters": r["n_iter"],
+                                     "solve_s": round(r["seconds"], 4)}}
+
+
+bench_bonds.solve = None
+
+
+def oracle_bonds_check():
+    """The oracle's Lanczos on the per-bond 3x4 solve (same seed and tol)."""
+    import oracle
+    e2, a2, e0 = bench_bonds.solve
+    m = oracle.Model(12, e2, 4, 4, a2, 8.0)
+    t0 = time.perf_counter()
+    r = m.lanczos(oracle.start_vector(12043425, m.dim), tol=1e-12, max_iter=400)
+    dt = time.perf_counter() - t0
+    return {"oracle_seconds": round(dt, 3), "gpu_E0_rel_err_vs_oracle": float("%.3g" % (abs(e0 - r["E0"]) / abs(r["E0"])))}
+
+
 def golden(name):
     """A stored oracle run (written by tests/golden/make_oracle_golden.py)."""
     path = os.path.join(ROOT, "tests", "golden", name)
@@ -587,6 +623,7 @@ def main():
     ap.add_argument("--serve", type=int, default=200, help="requests in the serving leg (0 skips it)")
     ap.add_argument("--no-small", action="store_true", help="skip the 14-site and 8-site ring legs")
     ap.add_argument("--propagate", type=int, default=1, help="real-time propagation leg (0 skips it)")
+    ap.add_argument("--bonds", type=int, default=1, help="per-bond amplitude leg (0 skips it)")
     ap.add_argument("--excited", type=int, default=3,
                     help="lowest states in the excited-state leg on the 4x4 lattice (0 skips it)")
     ap.add_argument("--summarize-trace")
@@ -686,6 +723,9 @@ def main():
         if not args.no_small:
             pr["ring8"] = bench_propagate(hb, torch, workload.ring8(), 1.0, 10, 16)
         out["propagation"] = pr
+    if args.bonds:
+        log("per-bond amplitude leg")
+        out["bonds"] = bench_bonds(hb, torch)
     batch_probs = None
     if args.batch:
         log("batch leg:", args.batch, "solves")
@@ -705,6 +745,9 @@ def main():
             cs = oracle_serving_check(bench_serving.results)
             if cs is not None:
                 cb["serving"] = cs
+        if bench_bonds.solve is not None:
+            log("oracle beside the per-bond leg")
+            cb["bonds"] = oracle_bonds_check()
         if bench_propagate.start:
             log("oracle beside the propagation leg")
             cb["propagation"] = oracle_propagate_check()

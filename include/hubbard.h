@@ -116,6 +116,22 @@ typedef struct {
 int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_dn, double t, double U,
                   hubbard_h *out);
 
+/* As hubbard_build with one hopping amplitude per bond: the hop over edge k
+ * has the element -t[k] * sgn (eq. H with t_ij in place of t; Sec. 2.1 notes
+ * that the construction holds for any lattice).  t: host array of n_edges
+ * finite values (NULL only when n_edges = 0).  If all t[k] are equal the
+ * handle is exactly the hubbard_build one.  Otherwise the amplitudes are
+ * grouped into classes of equal value (at most 127) whose index each table
+ * entry carries; such a handle runs the one-pass H.v kernel for every call
+ * (the two-pass kernels take one amplitude), runs unbatched in
+ * hubbard_lanczos_batch, and reports t = NaN in hubbard_info.
+ * Errors: as hubbard_build; EINVAL also for more than 127 distinct
+ * amplitudes or a non-finite one; ERANGE also when non-uniform amplitudes meet
+ * a spin dimension of 2^24 or more (the column must fit 24 bits beside the
+ * class). */
+int hubbard_build_bonds(int sites, const int32_t *edges, const double *t, int n_edges, int n_up, int n_dn, double U,
+                        hubbard_h *out);
+
 /* Releases the handle and its device memory.  NULL is accepted. */
 int hubbard_free(hubbard_h h);
 

@@ -107,6 +107,7 @@ def _load():
     vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     sig = {
         "hubbard_build": [i32, vp, i32, i32, i32, dbl, dbl, ctypes.POINTER(vp)],
+        "hubbard_build_bonds": [i32, vp, vp, i32, i32, i32, dbl, ctypes.POINTER(vp)],
         "hubbard_free": [vp],
         "hubbard_set_stream": [vp, vp],
         "hubbard_set_precision": [vp, i32],
@@ -220,6 +221,19 @@ def hubbard_build(sites, edges, n_up, n_dn, t=1.0, U=0.0) -> Handle:
     _check(_lib.hubbard_build(int(sites), e.ctypes.data_as(ctypes.c_void_p), len(e), int(n_up), int(n_dn),
                               float(t), float(U), ctypes.byref(out)), "hubbard_build")
     return Handle(out.value, sites, [tuple(x) for x in e.tolist()], n_up, n_dn, float(t), float(U))
+
+
+def hubbard_build_bonds(sites, edges, t, n_up, n_dn, U=0.0) -> Handle:
+    """As hubbard_build with one hopping amplitude per bond (t: sequence, one per edge)."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    a = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(-1))
+    if len(a) != len(e):
+        raise ValueError("one amplitude per edge expected")
+    out = ctypes.c_void_p()
+    _check(_lib.hubbard_build_bonds(int(sites), e.ctypes.data_as(ctypes.c_void_p),
+                                    a.ctypes.data_as(ctypes.c_void_p), len(e), int(n_up), int(n_dn), float(U),
+                                    ctypes.byref(out)), "hubbard_build_bonds")
+    return Handle(out.value, sites, [tuple(x) for x in e.tolist()], n_up, n_dn, a.copy(), float(U))
 
 
 def hubbard_free(h: Handle):

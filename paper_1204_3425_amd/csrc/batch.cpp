@@ -329,7 +329,8 @@ size_t batch_vector_bytes(const hubbard *h, int precision)
 bool batchable(const hubbard *h, int precision)
 {
     const size_t es = precision == HUBBARD_FP64 ? 8 : 4;
-    return h->device >= 0 && (size_t)h->dn.dim * es <= 64 * 1024;
+    // the batched kernels take one amplitude t for every hop
+    return h->device >= 0 && h->tcls.empty() && (size_t)h->dn.dim * es <= 64 * 1024;
 }
 
 void run_batch(hubbard **hs, const hubbard_opts *opts, hubbard_result *res, int n, hipStream_t s)

@@ -79,7 +79,12 @@ void build_spin_table(int sites, const std::vector<int32_t> &edges, int n, SpinT
     };
 
     const int ne = (int)edges.size() / 2;
-    std::vector<std::vector<std::pair<int32_t, int8_t>>> rows((size_t)out.dim);
+    struct Entry {
+        int32_t col;
+        int8_t sgn;
+        uint16_t bond;
+    };
+    std::vector<std::vector<Entry>> rows((size_t)out.dim);
     int32_t width = 0;
     int64_t nnz = 0;
     for (int64_t r = 0; r < out.dim; r++) {
@@ -91,10 +96,10 @@ void build_spin_table(int sites, const std::vector<int32_t> &edges, int n, SpinT
                 int lo = std::min(i, j), hi = std::max(i, j);
                 uint32_t between = (hi - lo > 1) ? (((1u << hi) - 1u) & ~((2u << lo) - 1u)) : 0u;
                 int8_t sg = (__builtin_popcount(s & between) & 1) ? -1 : 1;
-                row.emplace_back((int32_t)rank(s ^ ((1u << i) | (1u << j))), sg);
+                row.push_back(Entry{(int32_t)rank(s ^ ((1u << i) | (1u << j))), sg, (uint16_t)e});
             }
         }
-        std::sort(row.begin(), row.end(), [](auto &a, auto &b) { return a.first < b.first; });
+        std::sort(row.begin(), row.end(), [](const Entry &a, const Entry &b) { return a.col < b.col; });
         width = std::max<int32_t>(width, (int32_t)row.size());
         nnz += (int64_t)row.size();
     }
@@ -102,13 +107,15 @@ void build_spin_table(int sites, const std::vector<int32_t> &edges, int n, SpinT
     out.nnz = nnz;
     out.col.assign((size_t)width * (size_t)out.dim, 0);
     out.sgn.assign((size_t)width * (size_t)out.dim, 0);
+    out.bond.assign((size_t)width * (size_t)out.dim, 0);
     out.row_nnz.resize((size_t)out.dim);
     for (int64_t r = 0; r < out.dim; r++) {
         const auto &row = rows[(size_t)r];
         out.row_nnz[(size_t)r] = (uint16_t)row.size();
         for (size_t k = 0; k < row.size(); k++) {
-            out.col[k * (size_t)out.dim + (size_t)r] = row[k].first;
-            out.sgn[k * (size_t)out.dim + (size_t)r] = row[k].second;
+            out.col[k * (size_t)out.dim + (size_t)r] = row[k].col;
+            out.sgn[k * (size_t)out.dim + (size_t)r] = row[k].sgn;
+            out.bond[k * (size_t)out.dim + (size_t)r] = row[k].bond;
         }
     }
 }

@@ -98,7 +98,7 @@ static void free_device(hubbard *h)
     DeviceTables &d = h->dev;
     void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
                     d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.up_blk, d.up_nint, d.up_next,
-                    d.up_bstart, d.up_line, d.up_cnt};
+                    d.up_bstart, d.up_line, d.up_cnt, d.tcls};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -203,12 +203,18 @@ static void upload_tables(hubbard *h)
     size_t total = 0;
     d.states_up = upload<uint32_t>(h->up.states.data(), h->up.states.size() * 4, total);
     d.states_dn = upload<uint32_t>(h->dn.states.data(), h->dn.states.size() * 4, total);
+    // per-bond amplitudes: entries carry the amplitude class of their bond
+    const bool gen = !h->tcls.empty();
+    auto pack = [&](const SpinTable &tb, size_t src) {
+        return gen ? pack_entry_class(tb.col[src], tb.sgn[src], h->bond_cls[tb.bond[src]])
+                   : pack_entry(tb.col[src], tb.sgn[src]);
+    };
     // up table row-major (one row's entries are read by a whole workgroup)
     std::vector<uint32_t> rows((size_t)h->up.dim * (size_t)std::max(1, h->up.width), 0u);
     for (int64_t r = 0; r < h->up.dim; r++)
         for (int k = 0; k < h->up.row_nnz[(size_t)r]; k++) {
             size_t src = (size_t)k * (size_t)h->up.dim + (size_t)r;
-            rows[(size_t)r * (size_t)h->up.width + (size_t)k] = pack_entry(h->up.col[src], h->up.sgn[src]);
+            rows[(size_t)r * (size_t)h->up.width + (size_t)k] = pack(h->up, src);
         }
     d.up_rows = upload<uint32_t>(rows.data(), rows.size() * 4, total);
     // down table column-major (lanes of a wave read consecutive rows d)
@@ -216,11 +222,17 @@ static void upload_tables(hubbard *h)
     for (int64_t r = 0; r < h->dn.dim; r++)
         for (int k = 0; k < h->dn.row_nnz[(size_t)r]; k++) {
             size_t src = (size_t)k * (size_t)h->dn.dim + (size_t)r;
-            cols[src] = pack_entry(h->dn.col[src], h->dn.sgn[src]);
+            cols[src] = pack(h->dn, src);
         }
     d.dn_cols = upload<uint32_t>(cols.data(), cols.size() * 4, total);
     d.nnz_up = upload<uint16_t>(h->up.row_nnz.data(), h->up.row_nnz.size() * 2, total);
     d.nnz_dn = upload<uint16_t>(h->dn.row_nnz.data(), h->dn.row_nnz.size() * 2, total);
+    if (gen) {
+        // the one-pass kernel is the only one that reads amplitude classes
+        d.tcls = upload<double>(h->tcls.data(), h->tcls.size() * 8, total);
+        d.bytes = total;
+        return;
+    }
     // row-pass groups: entry k of column d at ((k/4) * dim_dn + d) * 4 + k%4
     const int64_t ddn = h->dn.dim;
     const int ng = (h->dn.width + 3) / 4;
@@ -269,6 +281,9 @@ static void upload_tables(hubbard *h)
 static HvArgs hv_args(const hubbard *h)
 {
     HvArgs a;
+    // per-bond handles: the device amplitudes; without a device only the plan
+    // reads this pointer, as the flag that selects the one-pass form
+    a.tcls = h->dev.tcls ? h->dev.tcls : (h->tcls.empty() ? nullptr : h->tcls.data());
     a.states_up = h->dev.states_up;
     a.states_dn = h->dev.states_dn;
     a.up_rows = h->dev.up_rows;
@@ -775,8 +790,9 @@ using namespace hub;
 
 extern "C" {
 
-int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_dn, double t, double U,
-                  hubbard_h *out)
+// amp: NULL (every bond has amplitude t) or one amplitude per bond.
+static int build_impl(int sites, const int32_t *edges, const double *amp, int n_edges, int n_up, int n_dn, double t,
+                      double U, hubbard_h *out)
 {
     return guarded([&]() -> int {
         if (!out)
@@ -803,11 +819,42 @@ int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_
             e[(size_t)2 * k] = i;
             e[(size_t)2 * k + 1] = j;
         }
+        // per-bond amplitudes: classes of equal value (all equal = the one-amplitude model)
+        std::vector<double> tcls;
+        std::vector<uint8_t> bond_cls;
+        if (amp) {
+            for (int k = 0; k < n_edges; k++)
+                if (!std::isfinite(amp[k]))
+                    fail(HUBBARD_EINVAL, "amplitude of edge " + std::to_string(k) + " is not finite");
+            bool uniform = true;
+            for (int k = 1; k < n_edges; k++)
+                uniform = uniform && amp[k] == amp[0];
+            if (uniform) {
+                t = n_edges > 0 ? amp[0] : 0.0;
+            } else {
+                bond_cls.resize((size_t)n_edges);
+                for (int k = 0; k < n_edges; k++) {
+                    size_t c = 0;
+                    while (c < tcls.size() && tcls[c] != amp[k])
+                        c++;
+                    if (c == tcls.size()) {
+                        if ((int)tcls.size() == kMaxAmpClasses)
+                            fail(HUBBARD_EINVAL, "more than " + std::to_string(kMaxAmpClasses) +
+                                                     " distinct hopping amplitudes");
+                        tcls.push_back(amp[k]);
+                    }
+                    bond_cls[(size_t)k] = (uint8_t)c;
+                }
+                t = NAN;
+            }
+        }
         const uint64_t du = binomial(sites, n_up), dd = binomial(sites, n_dn);
         // a spin dimension is at most C(32,16) < 2^31, so the sector size is the limit:
         // one vector of 2^40 elements would not fit the memory of any single device
         if ((long double)du * (long double)dd >= (long double)(1ull << 40))
             fail(HUBBARD_ERANGE, "sector dimension exceeds 2^40");
+        if (!tcls.empty() && (du >= (1ull << 24) || dd >= (1ull << 24)))
+            fail(HUBBARD_ERANGE, "per-bond amplitudes need spin dimensions below 2^24");
         std::unique_ptr<hubbard> h(new hubbard());
         h->sites = sites;
         h->n_up = n_up;
@@ -815,6 +862,8 @@ int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_
         h->t = t;
         h->U = U;
         h->edges = e;
+        h->tcls = tcls;
+        h->bond_cls = bond_cls;
         build_spin_table(sites, e, n_up, h->up);
         build_spin_table(sites, e, n_dn, h->dn);
         h->dim = h->up.dim * h->dn.dim;
@@ -834,6 +883,20 @@ int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_
         *out = h.release();
         return HUBBARD_OK;
     });
+}
+
+int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_dn, double t, double U,
+                  hubbard_h *out)
+{
+    return build_impl(sites, edges, nullptr, n_edges, n_up, n_dn, t, U, out);
+}
+
+int hubbard_build_bonds(int sites, const int32_t *edges, const double *t, int n_edges, int n_up, int n_dn, double U,
+                        hubbard_h *out)
+{
+    if (n_edges > 0 && !t)
+        return guarded([&]() -> int { fail(HUBBARD_EINVAL, "t is NULL"); });
+    return build_impl(sites, edges, t, n_edges, n_up, n_dn, 0.0, U, out);
 }
 
 int hubbard_free(hubbard_h h)

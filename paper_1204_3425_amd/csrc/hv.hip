@@ -762,7 +762,9 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
     pl.elem_bytes = elem_bytes;
     const int64_t ddn = a.dim_dn;
     const size_t one_row = (size_t)(ddn + 1) * (size_t)elem_bytes;
-    pl.two_pass = one_row <= (size_t)kLdsBytes;
+    // per-bond amplitudes run the one-pass kernel: the two-pass tables carry
+    // no amplitude class
+    pl.two_pass = one_row <= (size_t)kLdsBytes && !a.tcls;
     if (!pl.two_pass) {
         pl.ld = ddn;
         pl.nparts = hv_blocks(a, elem_bytes);

@@ -31,11 +31,20 @@ struct SpinTable {
     std::vector<int32_t> col;       // column-major ELL: entry k of row r at k*dim + r
     std::vector<int8_t> sgn;        // +1 / -1, padding 0
     std::vector<uint16_t> row_nnz;  // entries used in each row
+    std::vector<uint16_t> bond;     // column-major like col: the bond (edge index) of each entry
 };
 
 // Packed device form of a hopping entry: bits 0..30 column, bit 31 set when
 // the element is +t (sgn = -1).
 inline uint32_t pack_entry(int32_t col, int8_t sgn) { return (uint32_t)col | (sgn < 0 ? 0x80000000u : 0u); }
+// With per-bond amplitudes (columns below 2^24): bits 24..30 hold the
+// amplitude class, the element is -tcls[class] * sgn.
+inline uint32_t pack_entry_class(int32_t col, int8_t sgn, int cls)
+{
+    return (uint32_t)col | ((uint32_t)cls << 24) | (sgn < 0 ? 0x80000000u : 0u);
+}
+constexpr uint32_t kClassColMask = 0x00FFFFFFu;
+constexpr int kMaxAmpClasses = 127;
 
 struct DeviceTables {
     uint32_t *states_up = nullptr, *states_dn = nullptr;
@@ -64,6 +73,7 @@ struct DeviceTables {
     // counts packed as next << 16 | nint
     uint32_t *up_line = nullptr, *up_cnt = nullptr;
     size_t bytes = 0;
+    double *tcls = nullptr;  // amplitude of each class (per-bond amplitudes only)
 };
 
 }  // namespace hub
@@ -75,6 +85,8 @@ struct hubbard {
     hub::SpinTable up, dn;
     int64_t dim = 0;
     hub::DeviceTables dev;
+    std::vector<double> tcls;      // per-bond amplitudes: distinct values (empty: one amplitude t)
+    std::vector<uint8_t> bond_cls; // class of each bond
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = HUBBARD_FP64;
@@ -100,6 +112,9 @@ void tridiag_expm_e1(const double *d, const double *e, int m, double tau, double
 
 // kernels.hip: launchers (all asynchronous on `s`).
 struct HvArgs {
+    // per-bond amplitudes: the distinct values, indexed by the class bits of
+    // up_rows / dn_cols entries (NULL: every hop has amplitude t)
+    const double *tcls = nullptr;
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
     const uint4 *dn_groups64, *dn_groups32;

@@ -54,9 +54,13 @@ struct HvParams {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
     double t, U;
+    const double *__restrict__ tcls;
 };
 
-template <typename T, int MODE, bool STAGE>
+// GT: per-bond amplitudes, entry = column | class << 24 | sign << 31 and the
+// element is -tcls[class] * sgn; otherwise entry = column | sign << 31 and the
+// element is -t * sgn.
+template <typename T, int MODE, bool STAGE, bool GT>
 __global__ __launch_bounds__(1024) void hv_kernel(HvParams p, const T *__restrict__ x, T *__restrict__ y,
                                                   double alpha, double beta, const double *__restrict__ coef,
                                                   double *__restrict__ partials)
@@ -90,13 +94,26 @@ __global__ __launch_bounds__(1024) void hv_kernel(HvParams p, const T *__restric
             const int nd = p.nnz_dn[d];
             for (int k = 0; k < nd; k++) {
                 const uint32_t e = p.dn_cols[(int64_t)k * ddn + d];
-                const T v = STAGE ? xs[e & kColMask] : xr[e & kColMask];
-                h = fma((e >> 31) ? tp : tm, v, h);
+                if (GT) {
+                    const uint32_t c = e & kClassColMask;
+                    const T v = STAGE ? xs[c] : xr[c];
+                    const T a = (T)p.tcls[(e >> 24) & 0x7Fu];
+                    h = fma((e >> 31) ? a : -a, v, h);
+                } else {
+                    const T v = STAGE ? xs[e & kColMask] : xr[e & kColMask];
+                    h = fma((e >> 31) ? tp : tm, v, h);
+                }
             }
             for (int k = 0; k < nu; k++) {
                 const uint32_t e = urow[k];
-                const T v = x[(int64_t)(e & kColMask) * ddn + d];
-                h = fma((e >> 31) ? tp : tm, v, h);
+                if (GT) {
+                    const T v = x[(int64_t)(e & kClassColMask) * ddn + d];
+                    const T a = (T)p.tcls[(e >> 24) & 0x7Fu];
+                    h = fma((e >> 31) ? a : -a, v, h);
+                } else {
+                    const T v = x[(int64_t)(e & kColMask) * ddn + d];
+                    h = fma((e >> 31) ? tp : tm, v, h);
+                }
             }
             const int64_t J = r * ddn + d;
             if (MODE == HV_STORE) {
@@ -141,6 +158,7 @@ static HvParams to_params(const HvArgs &a)
     p.w_dn = a.w_dn;
     p.t = a.t;
     p.U = a.U;
+    p.tcls = a.tcls;
     return p;
 }
 
@@ -175,14 +193,15 @@ static void launch_hv_mode(const HvArgs &a, const T *x, T *y, double alpha, doub
 {
     const HvParams p = to_params(a);
     const int threads = hv_threads(a.dim_dn);
+    const bool gt = a.tcls != nullptr;
     if (hv_stage(a, sizeof(T))) {
         const size_t lds = (size_t)a.dim_dn * sizeof(T);
-        auto k = hv_kernel<T, MODE, true>;
+        auto k = gt ? hv_kernel<T, MODE, true, true> : hv_kernel<T, MODE, true, false>;
         HUB_HIP(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k, dim3(nblocks), dim3(threads), lds, s, p, x, y, alpha, beta, coef, partials);
     } else {
-        hipLaunchKernelGGL((hv_kernel<T, MODE, false>), dim3(nblocks), dim3(threads), 0, s, p, x, y, alpha, beta,
-                           coef, partials);
+        auto k = gt ? hv_kernel<T, MODE, false, true> : hv_kernel<T, MODE, false, false>;
+        hipLaunchKernelGGL(k, dim3(nblocks), dim3(threads), 0, s, p, x, y, alpha, beta, coef, partials);
     }
     HUB_HIP(hipGetLastError());
 }

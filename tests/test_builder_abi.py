@@ -226,3 +226,34 @@ def test_observables_validates_before_touching_the_device():
     assert lib.hubbard_observables(h.ptr, None, None, None, None) == hb.HUBBARD_EINVAL
     assert lib.hubbard_observables(None, 4096, None, None, None) == hb.HUBBARD_EINVAL
     assert lib.hubbard_observables(h.ptr, 4096, None, None, None) == hb.HUBBARD_EDEVICE
+
+
+def test_build_bonds_tables_and_validation():
+    """Per-bond amplitudes change only the values, not the table structure; all
+    amplitudes equal give the one-amplitude handle; bad amplitude lists fail
+    before anything is built."""
+    edges = workload.torus(2, 3)
+    amps = np.linspace(0.5, 1.5, len(edges))
+    hg = hb.hubbard_build_bonds(6, edges, amps, 3, 2, 2.0)
+    hu = hb.hubbard_build(6, edges, 3, 2, 1.0, 2.0)
+    for spin in (0, 1):
+        cg, sg = hb.hubbard_export_table(hg, spin)
+        cu, su = hb.hubbard_export_table(hu, spin)
+        assert np.array_equal(cg, cu) and np.array_equal(sg, su)
+    assert math.isnan(hb.hubbard_info(hg)["t"])
+    h1 = hb.hubbard_build_bonds(6, edges, [0.8] * len(edges), 3, 2, 2.0)
+    assert hb.hubbard_info(h1)["t"] == 0.8
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_build_bonds(6, edges, [1.0, float("nan")] + [1.0] * (len(edges) - 2), 3, 2, 2.0)
+    assert ei.value.code == hb.HUBBARD_EINVAL
+    # 136 bonds of a complete graph on 17 sites with 136 distinct amplitudes: above the 127 classes
+    full = [(i, j) for i in range(17) for j in range(i + 1, 17)]
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_build_bonds(17, full, np.arange(1, len(full) + 1, dtype=float), 1, 1, 0.0)
+    assert ei.value.code == hb.HUBBARD_EINVAL
+    # a spin dimension of 2^24 or more cannot hold the class bits (C(28,14) > 2^24)
+    with pytest.raises(hb.HubbardError) as ei:
+        hb.hubbard_build_bonds(28, workload.ring(28), np.linspace(1, 2, 28), 14, 1, 0.0)
+    assert ei.value.code == hb.HUBBARD_ERANGE
+    with pytest.raises(ValueError):
+        hb.hubbard_build_bonds(6, edges, [1.0], 3, 2, 2.0)

@@ -1,0 +1,125 @@
+"""GPU parity with one hopping amplitude per bond (hubbard_build_bonds: eq. H
+with t_ij for t) against the oracle's per-bond model.
+
+H.v: the same bound as the one-amplitude case (a sum of at most 1 + w_up + w_dn
+terms in a different order): max|y - y_ref| <= 1e-13 max|y_ref| in FP64 and
+the FP32 bound n u sum|terms| in mixed precision.  E0: 1e-10 relative (FP64),
+1e-6 (mixed), against the oracle's Lanczos from the same start vector.  The
+per-bond handle runs the one-pass kernel, with its row staged in LDS and
+(rows wider than LDS) not staged; both are covered.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+
+torch = pytest.importorskip("torch")
+hb = pytest.importorskip("paper_1204_3425_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _tt_prime_torus(lx, ly, t1, t2):
+    """Square lattice with nearest-neighbour bonds t1 and one diagonal per plaquette t2."""
+    nn = workload.torus(lx, ly)
+    diag = []
+    for y in range(ly):
+        for x in range(lx):
+            a, b = x + lx * y, (x + 1) % lx + lx * ((y + 1) % ly)
+            if a != b and (min(a, b), max(a, b)) not in {(min(i, j), max(i, j)) for i, j in nn + diag}:
+                diag.append((a, b))
+    return nn + diag, [t1] * len(nn) + [t2] * len(diag)
+
+
+CASES = [
+    # name, sites, edges, amplitudes, n_up, n_dn, U
+    ("ring8_random", 8, workload.ring(8), np.random.default_rng(1).uniform(-1.5, 1.5, 8), 4, 3, 3.0),
+    ("torus3x4_tprime", 12, *_tt_prime_torus(3, 4, 1.0, -0.35), 3, 3, 6.0),
+    ("chain10_ssh", 10, workload.chain(10), [1.0 if i % 2 == 0 else 0.4 for i in range(9)], 5, 5, 2.0),
+    # rows of 48,620 elements (18 sites, 9 down): wider than LDS, the kernel reads x directly
+    ("ring18_1u9d", 18, workload.ring(18), np.random.default_rng(2).uniform(0.5, 1.5, 18), 1, 9, 4.0),
+]
+
+
+@pytest.mark.parametrize("name,sites,edges,amps,nu,nd,U", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
+def test_bonds_apply_parity(name, sites, edges, amps, nu, nd, U, precision):
+    _say("apply", name, precision)
+    h = hb.hubbard_build_bonds(sites, edges, amps, nu, nd, U)
+    m = oracle.Model(sites, edges, nu, nd, amps, U)
+    x = workload.random_vector(m.dim, workload.BASE_SEED)
+    ref = m.apply(x)
+    hb.hubbard_set_precision(h, precision)
+    dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
+    xd = torch.from_numpy(x).to(DEV, dt)
+    yd = torch.empty_like(xd)
+    hb.hubbard_apply(h, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.double().cpu().numpy()
+    if precision == hb.HUBBARD_FP64:
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    else:
+        # FP32 accumulation of FP32 inputs: n u sum|terms| with n = 1 + w_up + w_dn
+        # terms, each hop at most max|t| max|x| and the diagonal U D_J x_J at most
+        # |U| min(N_up, N_dn) max|x|
+        info = hb.hubbard_info(h)
+        w = info["w_up"] + info["w_dn"]
+        xf = xd.double().cpu().numpy()  # the rounded input the GPU saw
+        S = (np.abs(amps).max() * w + abs(U) * min(nu, nd)) * np.abs(xf).max()
+        assert np.abs(y - m.apply(xf)).max() <= (1 + w) * 2.0 ** -24 * S
+
+
+@pytest.mark.parametrize("name,sites,edges,amps,nu,nd,U", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_bonds_lanczos_parity(name, sites, edges, amps, nu, nd, U):
+    _say("lanczos", name)
+    h = hb.hubbard_build_bonds(sites, edges, amps, nu, nd, U)
+    m = oracle.Model(sites, edges, nu, nd, amps, U)
+    ref = m.lanczos(oracle.start_vector(workload.BASE_SEED, m.dim), tol=1e-12, max_iter=400)
+    psi = torch.zeros(h.dim, dtype=torch.float64, device=DEV)
+    r = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=400, precision=hb.HUBBARD_FP64, seed=workload.BASE_SEED,
+                              psi=psi)
+    assert r["E0"] == pytest.approx(ref["E0"], rel=1e-10)
+    assert np.allclose(r["a"][:20], ref["a"][:20], rtol=1e-12, atol=1e-12)
+    assert r["residual"] <= 1e-4
+    rm = hb.hubbard_lanczos_ex(h, tol=1e-10, max_iter=400, precision=hb.HUBBARD_MIXED, seed=workload.BASE_SEED)
+    assert abs(rm["E0"] - ref["E0"]) <= 1e-6 * max(1.0, abs(ref["E0"]))
+
+
+def test_bonds_uniform_list_is_the_plain_handle():
+    """All amplitudes equal: the same handle as hubbard_build, bit for bit (two-pass kernels)."""
+    p = workload.ring8()
+    h1 = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    h2 = hb.hubbard_build_bonds(p.sites, p.edges, [p.t] * len(p.edges), p.n_up, p.n_dn, p.U)
+    r1 = hb.hubbard_lanczos_ex(h1, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=p.seed)
+    r2 = hb.hubbard_lanczos_ex(h2, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=p.seed)
+    assert r1["E0"] == r2["E0"] and np.array_equal(r1["a"], r2["a"])
+
+
+def test_bonds_through_lowest_states_propagate_and_batch():
+    """The other entry points run on a per-bond handle: lowest states against the
+    dense spectrum, propagation against the dense exponential, and the batch
+    call (which runs such a handle unbatched) against the single solve."""
+    sites, (edges, amps), nu, nd, U = 9, _tt_prime_torus(3, 3, 1.0, -0.35), 2, 2, 5.0  # dim 1,296
+    h = hb.hubbard_build_bonds(sites, edges, amps, nu, nd, U)
+    m = oracle.Model(sites, edges, nu, nd, amps, U)
+    w = m.lowest_states(3)[0]
+    E, _ = hb.hubbard_lowest_states(h, 3, tol=1e-14, max_iter=600, precision=hb.HUBBARD_FP64)
+    assert np.all(np.abs(E - w) <= 1e-10 * np.maximum(1.0, np.abs(w)))
+    g = np.random.default_rng(3)
+    psi0 = g.uniform(-1, 1, m.dim) + 1j * g.uniform(-1, 1, m.dim)
+    re = torch.from_numpy(psi0.real.copy()).to(DEV)
+    im = torch.from_numpy(psi0.imag.copy()).to(DEV)
+    hb.hubbard_propagate(h, re, im, 0.7, 5, 20)
+    got = re.cpu().numpy() + 1j * im.cpu().numpy()
+    assert np.abs(got - m.propagate(psi0, 0.7)).max() <= 1e-10 * np.linalg.norm(psi0)
+    single = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=7)
+    hu = hb.hubbard_build(8, workload.ring(8), 3, 3, 1.0, 2.0)
+    batch = hb.hubbard_lanczos_batch([h, hu], tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seeds=[7, 7])
+    assert batch[0]["E0"] == single["E0"]

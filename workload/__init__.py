@@ -9,7 +9,8 @@ periodic boundaries and a two-dimensional square lattice with periodic
 boundaries.  Sites of an Lx x Ly lattice are numbered x + Lx*y; bonds join
 (x, y) to (x+1 mod Lx, y) and to (x, y+1 mod Ly).  Each unordered bond appears
 once (a wrap-around bond that would repeat an existing one, as on a width-2
-lattice, is dropped).
+lattice, is dropped).  For per-bond amplitudes the square lattice also comes
+with next-nearest (diagonal) bonds and their own amplitude (the t-t' lattice).
 """
 from __future__ import annotations
 
@@ -52,6 +53,27 @@ def torus(lx: int, ly: int):
             pairs.append((s, (x + 1) % lx + lx * y))
             pairs.append((s, x + lx * ((y + 1) % ly)))
     return _dedupe(pairs)
+
+
+def torus_tprime(lx: int, ly: int, t1: float, t2: float):
+    """Bonds and per-bond amplitudes of the lx x ly periodic lattice with
+    nearest-neighbour hopping t1 and next-nearest (both diagonals) t2:
+    (edges, amplitudes), each unordered bond once."""
+    nn = torus(lx, ly)
+    diag = []
+    for y in range(ly):
+        for x in range(lx):
+            s = x + lx * y
+            diag.append((s, (x + 1) % lx + lx * ((y + 1) % ly)))
+            diag.append((s, (x + 1) % lx + lx * ((y - 1) % ly)))
+    seen = {(min(i, j), max(i, j)) for i, j in nn}
+    extra = []
+    for i, j in diag:
+        key = (min(i, j), max(i, j))
+        if i != j and key not in seen:
+            seen.add(key)
+            extra.append((i, j))
+    return nn + extra, [float(t1)] * len(nn) + [float(t2)] * len(extra)
 
 
 @dataclasses.dataclass(frozen=True)
