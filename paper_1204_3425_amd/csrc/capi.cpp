@@ -284,6 +284,7 @@ static HvArgs hv_args(const hubbard *h)
     // per-bond handles: the device amplitudes; without a device only the plan
     // reads this pointer, as the flag that selects the one-pass form
     a.tcls = h->dev.tcls ? h->dev.tcls : (h->tcls.empty() ? nullptr : h->tcls.data());
+    a.ncls = (int)h->tcls.size();
     a.states_up = h->dev.states_up;
     a.states_dn = h->dev.states_dn;
     a.up_rows = h->dev.up_rows;

@@ -115,6 +115,7 @@ struct HvArgs {
     // per-bond amplitudes: the distinct values, indexed by the class bits of
     // up_rows / dn_cols entries (NULL: every hop has amplitude t)
     const double *tcls = nullptr;
+    int ncls = 0;
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
     const uint4 *dn_groups64, *dn_groups32;

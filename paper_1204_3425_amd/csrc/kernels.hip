@@ -55,6 +55,7 @@ struct HvParams {
     int32_t w_up, w_dn;
     double t, U;
     const double *__restrict__ tcls;
+    int ncls;
 };
 
 // GT: per-bond amplitudes, entry = column | class << 24 | sign << 31 and the
@@ -72,6 +73,14 @@ __global__ __launch_bounds__(1024) void hv_kernel(HvParams p, const T *__restric
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[16];
+    // per-bond amplitudes of the classes, for the down-spin gathers (lanes read
+    // different classes)
+    __shared__ T amp[GT ? kMaxAmpClasses : 1];
+    if (GT) {
+        for (int c = threadIdx.x; c < p.ncls; c += blockDim.x)
+            amp[c] = (T)p.tcls[c];
+        __syncthreads();
+    }
 
     const int64_t ddn = p.dim_dn;
     const T tp = (T)p.t, tm = (T)(-p.t), U = (T)p.U;
@@ -97,23 +106,40 @@ __global__ __launch_bounds__(1024) void hv_kernel(HvParams p, const T *__restric
                 if (GT) {
                     const uint32_t c = e & kClassColMask;
                     const T v = STAGE ? xs[c] : xr[c];
-                    const T a = (T)p.tcls[(e >> 24) & 0x7Fu];
+                    const T a = amp[(e >> 24) & 0x7Fu];
                     h = fma((e >> 31) ? a : -a, v, h);
                 } else {
                     const T v = STAGE ? xs[e & kColMask] : xr[e & kColMask];
                     h = fma((e >> 31) ? tp : tm, v, h);
                 }
             }
-            for (int k = 0; k < nu; k++) {
-                const uint32_t e = urow[k];
+            // up-spin hops read other rows of x from memory: eight loads are
+            // issued before their products are summed
+            auto up_term = [&](uint32_t e, T v) {
                 if (GT) {
-                    const T v = x[(int64_t)(e & kClassColMask) * ddn + d];
-                    const T a = (T)p.tcls[(e >> 24) & 0x7Fu];
-                    h = fma((e >> 31) ? a : -a, v, h);
-                } else {
-                    const T v = x[(int64_t)(e & kColMask) * ddn + d];
-                    h = fma((e >> 31) ? tp : tm, v, h);
+                    const T a = amp[(e >> 24) & 0x7Fu];
+                    return (e >> 31) ? a * v : -a * v;
                 }
+                return (e >> 31) ? tp * v : tm * v;
+            };
+            const uint32_t cmask = GT ? kClassColMask : kColMask;
+            int k = 0;
+            for (; k + 8 <= nu; k += 8) {
+                uint32_t e[8];
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    e[u] = urow[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    v[u] = x[(int64_t)(e[u] & cmask) * ddn + d];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    h += up_term(e[u], v[u]);
+            }
+            for (; k < nu; k++) {
+                const uint32_t e = urow[k];
+                h += up_term(e, x[(int64_t)(e & cmask) * ddn + d]);
             }
             const int64_t J = r * ddn + d;
             if (MODE == HV_STORE) {
@@ -159,6 +185,7 @@ static HvParams to_params(const HvArgs &a)
     p.t = a.t;
     p.U = a.U;
     p.tcls = a.tcls;
+    p.ncls = a.ncls;
     return p;
 }
 
@@ -168,8 +195,12 @@ static int hv_threads(int64_t dim_dn)
     return (int)(t < 1024 ? t : 1024);
 }
 
-// the row must fit in LDS beside the kernel's small static arrays
-static bool hv_stage(const HvArgs &a, int elem_bytes) { return a.dim_dn * elem_bytes <= 160 * 1024 - 512; }
+// the row must fit in LDS beside the kernel's small static arrays (and the
+// amplitude classes of a per-bond handle)
+static bool hv_stage(const HvArgs &a, int elem_bytes)
+{
+    return a.dim_dn * elem_bytes <= 160 * 1024 - 512 - (a.tcls ? 1024 : 0);
+}
 
 int hv_blocks(const HvArgs &a, int elem_bytes)
 {
