@@ -100,6 +100,8 @@ typedef struct {
     int32_t stop;       /* HUBBARD_STOP_* */
     int32_t status;     /* HUBBARD_OK or HUBBARD_ENOCONV, or an error code */
     int32_t precision;
+    int32_t psi_resident; /* 1: psi was combined from the Lanczos vectors kept on the device;
+                             0: from the replayed recurrence (or psi not requested) */
 } hubbard_result;
 
 /* Builds the basis of each spin (ascending configuration words, combinatorial
@@ -144,6 +146,15 @@ int hubbard_set_stream(hubbard_h h, void *hip_stream);
 /* Arithmetic of hubbard_apply and hubbard_lanczos: HUBBARD_FP64 (default) or
  * HUBBARD_MIXED. */
 int hubbard_set_precision(hubbard_h h, int precision);
+
+/* Device bytes that a solve with psi requested may hold for its resident
+ * Lanczos basis (default: no limit beyond the free memory less 2 GiB).  While
+ * the basis fits, every stored Lanczos vector is copied to a slot of its own as
+ * the first pass runs and psi = sum_j y_j f_j is one pass over them (Sec. 2.2
+ * obtains psi from the same sum); otherwise, or with 0, the slots are freed and
+ * the recurrence is replayed to accumulate psi, as without the basis.  Both give
+ * psi to rounding; hubbard_result.psi_resident tells which ran. */
+int hubbard_set_basis_limit(hubbard_h h, size_t bytes);
 
 /* Seed of the start vector used by hubbard_lanczos (default 12043425). */
 int hubbard_set_seed(hubbard_h h, uint64_t seed);

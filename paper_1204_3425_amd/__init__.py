@@ -64,7 +64,7 @@ class hubbard_result(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("residual", ctypes.c_double), ("rayleigh", ctypes.c_double),
                 ("err_est", ctypes.c_double), ("seconds", ctypes.c_double), ("seconds_per_iter", ctypes.c_double),
                 ("n_iter", ctypes.c_int32), ("stop", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("psi_resident", ctypes.c_int32)]
 
 
 class hubbard_prop_result(ctypes.Structure):
@@ -112,6 +112,7 @@ def _load():
         "hubbard_set_stream": [vp, vp],
         "hubbard_set_precision": [vp, i32],
         "hubbard_set_seed": [vp, u64],
+        "hubbard_set_basis_limit": [vp, ctypes.c_size_t],
         "hubbard_apply": [vp, vp, vp],
         "hubbard_apply_ld": [vp, vp, i64, vp, i64],
         "hubbard_lanczos": [vp, dbl, i32, ctypes.POINTER(dbl), vp],
@@ -253,6 +254,10 @@ def hubbard_set_precision(h: Handle, precision: int):
     h.precision = int(precision)
 
 
+def hubbard_set_basis_limit(h: Handle, nbytes: int):
+    _check(_lib.hubbard_set_basis_limit(h, int(nbytes)), "hubbard_set_basis_limit")
+
+
 def hubbard_set_seed(h: Handle, seed: int):
     _check(_lib.hubbard_set_seed(h, int(seed) & (2**64 - 1)), "hubbard_set_seed")
 
@@ -310,7 +315,7 @@ def _result_dict(r: hubbard_result, hist):
     m = r.n_iter
     out = {"E0": r.e0, "n_iter": m, "stop": STOP_NAMES.get(r.stop, r.stop), "status": r.status,
            "residual": r.residual, "rayleigh": r.rayleigh, "err_est": r.err_est, "seconds": r.seconds,
-           "seconds_per_iter": r.seconds_per_iter, "precision": r.precision}
+           "seconds_per_iter": r.seconds_per_iter, "precision": r.precision, "psi_resident": r.psi_resident}
     if hist is not None:
         out["a"], out["b"], out["e_hist"] = hist[0][:m].copy(), hist[1][:m].copy(), hist[2][:m].copy()
     return out

@@ -335,10 +335,36 @@ struct LanczosOut {
     int stop = HUBBARD_STOP_MAXITER;
     double e0 = 0, residual = -1, rayleigh = NAN;
     double seconds_first = 0;
+    bool psi_resident = false;  // psi came from the resident vectors, not a replay
 };
 
 // sectors from this size on take the fused Lanczos step
 constexpr int64_t kFusedMinDim = 1 << 16;
+
+// Slots for a resident Lanczos basis, allocated in chunks of kBasisChunk
+// vectors as a run needs them and reusable by the next run of the same call.
+constexpr size_t kBasisChunk = 32;
+struct BasisPool {
+    std::vector<std::unique_ptr<DevBuf>> chunks;
+    size_t vb = 0;  // bytes per vector
+    size_t capacity() const { return chunks.size() * kBasisChunk; }
+    void *slot(size_t j) const { return static_cast<char *>(chunks[j / kBasisChunk]->p) + (j % kBasisChunk) * vb; }
+    // room for vector j within budget (bytes the pool may hold in total); false when it cannot grow
+    bool reserve(size_t j, size_t budget)
+    {
+        while (j >= capacity()) {
+            if ((chunks.size() + 1) * kBasisChunk * vb > budget)
+                return false;
+            try {
+                chunks.emplace_back(new DevBuf(kBasisChunk * vb));
+            } catch (const Error &) {
+                (void)hipGetLastError();
+                return false;
+            }
+        }
+        return true;
+    }
+};
 
 // Lower eigenvectors to project out of every Lanczos vector (FP64, dense J
 // order, vector l at psi + l * dim), nd of them.
@@ -348,7 +374,8 @@ struct Deflation {
 };
 
 template <typename T>
-static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, const Deflation &dfl = Deflation())
+static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, const Deflation &dfl = Deflation(),
+                        BasisPool *pool_in = nullptr)
 {
     const int64_t n = h->dim;
     const HvArgs args = hv_args(h);
@@ -455,6 +482,42 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
         }
     } evguard{ev};
 
+    // Resident basis: with psi requested, every stored Lanczos vector (and its
+    // scale) is copied to a slot of its own while the device has room (and the
+    // handle's basis limit allows), so psi is one combination pass over them
+    // instead of a replay of the whole recurrence.  Running out of room frees
+    // the slots and falls back to the replay.
+    BasisPool local_pool;
+    BasisPool &pool = pool_in ? *pool_in : local_pool;
+    bool resident = o.psi != nullptr;
+    size_t basis_budget = 0;
+    if (resident) {
+        const size_t vb = sizeof(T) * (size_t)npad;
+        if (pool.vb != vb) {
+            HUB_HIP(hipDeviceSynchronize());
+            pool.chunks.clear();
+            pool.vb = vb;
+        }
+        size_t fr = 0, tot = 0;
+        HUB_HIP(hipMemGetInfo(&fr, &tot));
+        const size_t reserve = (size_t)2 << 30;
+        const size_t held = pool.chunks.size() * kBasisChunk * vb;
+        basis_budget = std::min(held + (fr > reserve ? fr - reserve : 0), h->basis_limit);
+    }
+    DevBuf scales(o.psi ? sizeof(double) * (size_t)max_iter : 0);
+    auto keep = [&](const T *C, int j0) {
+        if (!resident)
+            return;
+        if (!pool.reserve((size_t)j0, basis_budget)) {
+            resident = false;
+            HUB_HIP(hipStreamSynchronize(s));
+            pool.chunks.clear();
+            return;
+        }
+        HUB_HIP(hipMemcpyAsync(pool.slot((size_t)j0), C, pool.vb, hipMemcpyDeviceToDevice, s));
+        HUB_HIP(hipMemcpyAsync(scales.as<double>() + j0, S, sizeof(double), hipMemcpyDeviceToDevice, s));
+    };
+
     T *bufs[2] = {vecs[0], vecs[1]};
     auto t0 = std::chrono::steady_clock::now();
     start_pass(bufs[0], bufs[1]);
@@ -474,7 +537,16 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     while (!stop) {
         if (launched < max_iter) {
             const int j0 = launched;  // 0-based step index
-            step(bufs[j0 & 1], bufs[(j0 + 1) & 1], j0);
+            T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
+            if (fused) {
+                // f_j exists once the step's row pass has formed it; S[0] still holds 1/s_j
+                const int np = hv_step(C, P);
+                keep(C, j0);
+                finish_step(C, P, np, j0);
+            } else {
+                keep(C, j0);
+                step(C, P, j0);
+            }
             HUB_HIP(hipMemcpyAsync(hh + 2 * j0, hist + 2 * j0, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
             HUB_HIP(hipEventRecord(ev[(size_t)(j0 % nev)], s));
             launched++;
@@ -525,24 +597,42 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
 
     if (!o.psi)
         return;
-    // ---- second pass: replay the identical recurrence and accumulate psi
     const int m = out.m;
     std::vector<double> y((size_t)m);
     tridiag_lowest_vector(out.a.data(), out.b.data(), m, out.e0, y.data());
-    start_pass(bufs[0], bufs[1]);
-    for (int j0 = 0; j0 < m; j0++) {
-        T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
-        if (fused) {
-            // f_j exists once the step's row pass has formed it; S[0] still holds 1/s_j
-            const int np = hv_step(C, P);
+    out.psi_resident = resident && pool.capacity() >= (size_t)m;
+    if (out.psi_resident) {
+        // ---- psi = sum_j y_j f_j from the resident vectors
+        std::vector<const T *> ptrs((size_t)m);
+        for (int j = 0; j < m; j++)
+            ptrs[(size_t)j] = static_cast<const T *>(pool.slot((size_t)j));
+        DevBuf dptr(sizeof(const T *) * (size_t)m), dy(sizeof(double) * (size_t)m);
+        HUB_HIP(hipMemcpyAsync(dptr.p, ptrs.data(), sizeof(const T *) * (size_t)m, hipMemcpyHostToDevice, s));
+        HUB_HIP(hipMemcpyAsync(dy.p, y.data(), sizeof(double) * (size_t)m, hipMemcpyHostToDevice, s));
+        launch_psi_combine<T>(o.psi, dptr.as<const T *>(), dy.as<double>(), scales.as<double>(), m, h->up.dim,
+                              h->dn.dim, ld, s);
+        HUB_HIP(hipStreamSynchronize(s));
+    } else {
+        // ---- second pass: replay the identical recurrence and accumulate psi
+        if (!pool.chunks.empty()) {
+            HUB_HIP(hipStreamSynchronize(s));
+            pool.chunks.clear();
+        }
+        start_pass(bufs[0], bufs[1]);
+        for (int j0 = 0; j0 < m; j0++) {
+            T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
+            if (fused) {
+                // f_j exists once the step's row pass has formed it; S[0] still holds 1/s_j
+                const int np = hv_step(C, P);
+                launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, h->up.dim, h->dn.dim, ld, j0 == 0, s);
+                if (j0 + 1 < m)
+                    finish_step(C, P, np, j0);
+                continue;
+            }
             launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, h->up.dim, h->dn.dim, ld, j0 == 0, s);
             if (j0 + 1 < m)
-                finish_step(C, P, np, j0);
-            continue;
+                step(C, P, j0);
         }
-        launch_psi_acc<T>(o.psi, C, y[(size_t)j0], S, h->up.dim, h->dn.dim, ld, j0 == 0, s);
-        if (j0 + 1 < m)
-            step(C, P, j0);
     }
     // the accumulated vector is projected once more, so that it is orthogonal
     // to the lower states to rounding
@@ -598,6 +688,7 @@ static hubbard_result make_result(const LanczosOut &out, const hubbard_opts &o, 
     r.stop = out.stop;
     r.status = status;
     r.precision = o.precision;
+    r.psi_resident = (o.psi && out.psi_resident) ? 1 : 0;
     return r;
 }
 
@@ -652,6 +743,7 @@ int lowest_states_impl(hubbard *h, int k, const hubbard_opts &o, double *E, doub
         base = own->as<double>();
     }
     int worst = HUBBARD_OK;
+    BasisPool pool;  // the resident basis slots, reused by every state
     for (int i = 0; i < k; i++) {
         auto t0 = std::chrono::steady_clock::now();
         // an independent start vector per state: a start shared by all of them
@@ -668,9 +760,9 @@ int lowest_states_impl(hubbard *h, int k, const hubbard_opts &o, double *E, doub
         d.nd = i;
         LanczosOut out;
         if (o.precision == HUBBARD_FP64)
-            run_lanczos<double>(h, oi, out, d);
+            run_lanczos<double>(h, oi, out, d, &pool);
         else
-            run_lanczos<float>(h, oi, out, d);
+            run_lanczos<float>(h, oi, out, d, &pool);
         auto t1 = std::chrono::steady_clock::now();
         const int status = status_of(out, oi);
         E[i] = out.e0;
@@ -930,6 +1022,15 @@ int hubbard_set_precision(hubbard_h h, int precision)
         if (precision != HUBBARD_FP64 && precision != HUBBARD_MIXED)
             fail(HUBBARD_EINVAL, "unknown precision");
         h->precision = precision;
+        return HUBBARD_OK;
+    });
+}
+
+int hubbard_set_basis_limit(hubbard_h h, size_t bytes)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        h->basis_limit = bytes;
         return HUBBARD_OK;
     });
 }

@@ -91,6 +91,8 @@ struct hubbard {
     hipStream_t stream = nullptr;
     int precision = HUBBARD_FP64;
     uint64_t seed = 12043425ull;
+    // device bytes a solve with psi may hold for its resident Lanczos basis
+    size_t basis_limit = SIZE_MAX;
 };
 
 namespace hub {
@@ -186,6 +188,10 @@ void launch_psi_acc(double *psi, const T *v, double yj, const double *coef, int6
                     bool first, hipStream_t s);
 void launch_psi_stats(const double *psi, const double *given, uint64_t seed, int64_t n, double *partials, int nblocks,
                       hipStream_t s);
+// psi[r*dim_dn + d] = sum_{j < m} y[j] * scale[j] * vecs[j][r*ld + d] (the resident Lanczos vectors)
+template <typename T>
+void launch_psi_combine(double *psi, const T *const *vecs, const double *y, const double *scale, int m, int64_t dim_up,
+                        int64_t dim_dn, int64_t ld, hipStream_t s);
 void launch_scale(double *v, double c, int64_t n, hipStream_t s);
 void launch_reduce(const double *partials, int n, int stride, int count, double *out, hipStream_t s);
 // observables.hip: unnormalised sums UU, DD, C (NS x NS each, NS = obs_ns_max)

@@ -526,6 +526,37 @@ template void launch_psi_acc<double>(double *, const double *, double, const dou
 template void launch_psi_acc<float>(double *, const float *, double, const double *, int64_t, int64_t, int64_t, bool,
                                     hipStream_t);
 
+// psi = sum_j y_j (1/s_j) v_j over the resident Lanczos vectors, summed in the
+// order of the replayed accumulation
+template <typename T>
+__global__ __launch_bounds__(256) void psi_combine_kernel(double *__restrict__ psi, const T *const *__restrict__ vecs,
+                                                          const double *__restrict__ y,
+                                                          const double *__restrict__ scale, int m, int64_t dim_up,
+                                                          int64_t dim_dn, int64_t ld)
+{
+    ROW_LOOP(r, d, dim_up, dim_dn)
+    {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < m; j++)
+            acc += (y[j] * scale[j]) * (double)vecs[j][r * ld + d];
+        psi[r * dim_dn + d] = acc;
+    }
+}
+
+template <typename T>
+void launch_psi_combine(double *psi, const T *const *vecs, const double *y, const double *scale, int m, int64_t dim_up,
+                        int64_t dim_dn, int64_t ld, hipStream_t s)
+{
+    hipLaunchKernelGGL(psi_combine_kernel<T>, dim3(row_blocks(dim_up)), dim3(256), 0, s, psi, vecs, y, scale, m,
+                       dim_up, dim_dn, ld);
+    HUB_HIP(hipGetLastError());
+}
+template void launch_psi_combine<double>(double *, const double *const *, const double *, const double *, int, int64_t,
+                                         int64_t, int64_t, hipStream_t);
+template void launch_psi_combine<float>(double *, const float *const *, const double *, const double *, int, int64_t,
+                                        int64_t, int64_t, hipStream_t);
+
 // partial sums of psi.psi and psi.f1
 __global__ __launch_bounds__(256) void psi_stats_kernel(const double *__restrict__ psi, const double *__restrict__ given,
                                                         uint64_t seed, int64_t n, double *__restrict__ partials)

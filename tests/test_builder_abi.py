@@ -257,3 +257,12 @@ def test_build_bonds_tables_and_validation():
     assert ei.value.code == hb.HUBBARD_ERANGE
     with pytest.raises(ValueError):
         hb.hubbard_build_bonds(6, edges, [1.0], 3, 2, 2.0)
+
+
+def test_basis_limit_setter():
+    h = hb.hubbard_build(4, workload.ring(4), 2, 2, 1.0, 2.0)
+    hb.hubbard_set_basis_limit(h, 0)
+    hb.hubbard_set_basis_limit(h, 2 ** 40)
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    lib.hubbard_set_basis_limit.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    assert lib.hubbard_set_basis_limit(None, 0) == hb.HUBBARD_EINVAL
