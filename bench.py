@@ -527,7 +527,7 @@ def _kernel_family(name):
                 "obs_sum_groups_kernel", "obs_sum_kernel", "psi_stats_kernel", "scale_kernel",
                 "prop_load_kernel", "prop_update_kernel", "prop_combine_kernel", "prop_reduce_kernel",
                 "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
-                "psi_acc_kernel", "copyBuffer", "elementwise"):
+                "psi_acc_kernel", "psi_combine_kernel", "copyBuffer", "elementwise"):
         if fam in name:
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""
