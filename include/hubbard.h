@@ -182,9 +182,10 @@ int hubbard_apply_ld(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t l
 /* Lanczos ground state (Sec. 2.2, Alg. 1, two-vector form): iterates until
  * the energy test passes with tol (> 0), b_{j+1} vanishes, or max_iter (>= 1)
  * steps.  Writes the lowest Ritz value to *E0 (host).  psi: NULL, or a device
- * FP64 array of dim elements receiving the ground-state vector (a second,
- * replayed pass).  Synchronous.  Returns OK, or ENOCONV when max_iter was hit
- * first (E0 still written). */
+ * FP64 array of dim elements receiving the ground-state vector, combined from
+ * the Lanczos vectors kept on the device (or accumulated by a replayed pass
+ * when they do not fit; hubbard_set_basis_limit).  Synchronous.  Returns OK,
+ * or ENOCONV when max_iter was hit first (E0 still written). */
 int hubbard_lanczos(hubbard_h h, double tol, int max_iter, double *E0, double *psi);
 
 /* As hubbard_lanczos with every option and the full result record. */
@@ -194,8 +195,8 @@ int hubbard_lanczos_ex(hubbard_h h, const hubbard_opts *opts, hubbard_result *re
  * eigenvectors (Sec. 2.2: the ground state and the lowest excited states),
  * found one after another: state i is the ground state of P H P with
  * P = 1 - sum_{l<i} psi_l psi_l^T, run as Alg. 1 with every new Lanczos vector
- * projected through P (the start vector too), followed by the replayed pass
- * that accumulates psi_i; psi_i is projected once more, normalised and signed
+ * projected through P (the start vector too); psi_i is then formed from its
+ * Lanczos vectors as for hubbard_lanczos, projected once more, normalised and signed
  * so that <psi_i, f1^(i)> > 0.  State i starts from its own vector f1^(i): the
  * seeded vector of hubbard_start_raw with seed opts->seed + i (state 0 from
  * opts->start when that is given).  Separate starts are what lets a degenerate
