@@ -169,7 +169,9 @@ static void upload_blocked_up(hubbard *h, size_t &total)
                 if (inside != (pass == 0))
                     continue;
                 const uint32_t sg = up.sgn[src] < 0 ? 0x80000000u : 0u;
-                ent[o++] = (uint32_t)(inside ? c - bstart[(size_t)b] : c) | sg;
+                // per-bond handles: the amplitude class in bits 24..25 (rows below 2^24)
+                const uint32_t cls = h->tcls.empty() ? 0u : (uint32_t)h->bond_cls[up.bond[src]] << 24;
+                ent[o++] = (uint32_t)(inside ? c - bstart[(size_t)b] : c) | cls | sg;
                 (inside ? ni : ne)++;
             }
         nint[(size_t)r] = (uint16_t)ni;
@@ -228,11 +230,15 @@ static void upload_tables(hubbard *h)
     d.nnz_up = upload<uint16_t>(h->up.row_nnz.data(), h->up.row_nnz.size() * 2, total);
     d.nnz_dn = upload<uint16_t>(h->dn.row_nnz.data(), h->dn.row_nnz.size() * 2, total);
     if (gen) {
-        // the one-pass kernel is the only one that reads amplitude classes
         d.tcls = upload<double>(h->tcls.data(), h->tcls.size() * 8, total);
-        d.bytes = total;
-        return;
+        if ((int)h->tcls.size() > kTwoPassClasses) {
+            // only the one-pass kernel reads this many classes
+            d.bytes = total;
+            return;
+        }
     }
+    // class bits of an entry of the down table (per-bond handles)
+    auto dn_cls = [&](size_t src) -> uint32_t { return gen ? (uint32_t)h->bond_cls[h->dn.bond[src]] : 0u; };
     // row-pass groups: entry k of column d at ((k/4) * dim_dn + d) * 4 + k%4
     const int64_t ddn = h->dn.dim;
     const int ng = (h->dn.width + 3) / 4;
@@ -249,6 +255,10 @@ static void upload_tables(hubbard *h)
             for (int k = 0; k < h->dn.row_nnz[(size_t)r]; k++) {
                 size_t src = (size_t)k * (size_t)ddn + (size_t)r;
                 uint32_t off = (uint32_t)h->dn.col[src] * (uint32_t)es;
+                // classes sit above the offset (bits 18..19): offsets of the rows
+                // the two-pass plan stages in LDS stay below 2^18
+                if (gen && off < (1u << 18))
+                    off |= dn_cls(src) << 18;
                 g[((size_t)(k / 4) * (size_t)ddn + (size_t)r) * 4 + (size_t)(k % 4)] =
                     off | (h->dn.sgn[src] < 0 ? 0x80000000u : 0u);
             }
@@ -256,7 +266,7 @@ static void upload_tables(hubbard *h)
         (es == 8 ? d.dn_groups64 : d.dn_groups32) = dev;
     }
     d.dn_nq = upload<uint8_t>(nq.data(), nq.size(), total);
-    if (ddn < 32768) {
+    if (ddn < 32768 && !gen) {
         // entry k of column d at ((k/8) * dim_dn + d) * 8 + k%8; padding = the zero slot's index
         const int ng8 = (h->dn.width + 7) / 8;
         std::vector<uint16_t> g((size_t)std::max(ng8, 1) * (size_t)ddn * 8, (uint16_t)ddn);
@@ -285,6 +295,8 @@ static HvArgs hv_args(const hubbard *h)
     // reads this pointer, as the flag that selects the one-pass form
     a.tcls = h->dev.tcls ? h->dev.tcls : (h->tcls.empty() ? nullptr : h->tcls.data());
     a.ncls = (int)h->tcls.size();
+    for (int c = 0; c < a.ncls && c < 4; c++)
+        a.amp4[c] = h->tcls[(size_t)c];
     a.states_up = h->dev.states_up;
     a.states_dn = h->dev.states_dn;
     a.up_rows = h->dev.up_rows;

@@ -90,11 +90,24 @@ struct RowArgs {
     int64_t dim_up, dim_dn;
     int ngroups;
     double t, U;
+    double amp[4];  // per-bond amplitude classes (GT kernels)
 };
+
+// Per-bond amplitudes (GT kernels): entries carry a class of at most four
+// amplitudes, bits 24..25 of an up-spin entry (row below 2^24) and bits 18..19
+// of a row-pass group entry (byte offset below 2^18); the element is
+// -amp[class] * sgn, so the class amplitude multiplies the signed value and
+// the final factor is -1 instead of -t.
+template <typename T>
+__device__ inline T class_amp(const T (&a)[4], uint32_t c)
+{
+    return c == 0 ? a[0] : (c == 1 ? a[1] : (c == 2 ? a[2] : a[3]));
+}
+constexpr uint32_t kGtRowMask = 0x00FFFFFFu;
 
 // Row pass.  MODE as in the file comment; for HV_RESIDUAL y is the scratch
 // vector z and alpha is the shift.
-template <typename T, int RPB, int MODE, bool G16>
+template <typename T, int RPB, int MODE, bool G16, bool GT>
 __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__restrict__ x, int64_t ldx,
                                                        T *__restrict__ y, int64_t ldy, double alpha, double beta,
                                                        const double *__restrict__ coef)
@@ -112,7 +125,8 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
     }
     const int64_t ddn = p.dim_dn;
     const int64_t slot = ddn + 1;  // staged row length including the zero slot
-    const T mt = (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta, c_s = (T)cshift;
+    const T mt = GT ? (T)(-1) : (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta, c_s = (T)cshift;
+    const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     // staging: each thread loads CH elements of each of the RPB rows before it
     // writes any of them to LDS, so a row costs one or two memory round trips
     constexpr int CH = (MODE == HV_FUSED ? 8 : 16) / RPB;
@@ -189,14 +203,18 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                                 off = (e & 0x7fffu) * (uint32_t)sizeof(T);
                                 sg = (e & 0x8000u) << 16;
                             } else {
-                                off = ev[u] & 0x7fffffffu;
+                                off = ev[u] & (GT ? 0x3ffffu : 0x7fffffffu);
                                 sg = ev[u] & 0x80000000u;
                             }
+                            const T ac = GT ? class_amp(am, (ev[u] >> 18) & 3u) : (T)1;
 #pragma unroll
                             for (int q = 0; q < RPB; q++) {
                                 const T v = *reinterpret_cast<const T *>(
                                     reinterpret_cast<const unsigned char *>(xs + q * slot) + off);
-                                h[q] += flip_sign(v, sg);
+                                if (GT)
+                                    h[q] += ac * flip_sign(v, sg);
+                                else
+                                    h[q] += flip_sign(v, sg);
                             }
                         }
                     }
@@ -230,10 +248,11 @@ struct SlabArgs {
     int64_t dim_up, dim_dn;
     int w_up, rows_per_wg, nslab;
     double t;
+    double amp[4];
 };
 
 // Slab pass.  y holds the row-pass result and receives the complete product.
-template <typename T, int MODE>
+template <typename T, int MODE, bool GT>
 __global__ __launch_bounds__(kSlabThreads) void hv_slabs_kernel(SlabArgs p, const T *__restrict__ x, int64_t ldx,
                                                                 T *__restrict__ y, int64_t ldy, double alpha,
                                                                 const double *__restrict__ coef,
@@ -245,7 +264,8 @@ __global__ __launch_bounds__(kSlabThreads) void hv_slabs_kernel(SlabArgs p, cons
     __shared__ double red[4];
     if (MODE == HV_LANCZOS)
         alpha = coef[0];
-    const T a_s = (T)alpha, tp = (T)p.t, tm = (T)(-p.t);
+    const T a_s = (T)alpha, tp = (T)p.t;
+    const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int xcd = blockIdx.x & 7;
     const int64_t local = blockIdx.x >> 3;
@@ -278,8 +298,9 @@ __global__ __launch_bounds__(kSlabThreads) void hv_slabs_kernel(SlabArgs p, cons
                 for (int u = 0; u < UNR; u++) {
                     const bool live = k0 + u < n;
                     const uint32_t e = er[live ? k0 + u : 0];
-                    c[u] = live ? (int64_t)(e & 0x7fffffffu) : r;
-                    cf[u] = live ? ((e >> 31) ? tp : tm) : (T)0;
+                    c[u] = live ? (int64_t)(e & (GT ? kGtRowMask : 0x7fffffffu)) : r;
+                    const T ap = GT ? class_amp(am, (e >> 24) & 3u) : tp;
+                    cf[u] = live ? ((e >> 31) ? ap : -ap) : (T)0;
                 }
                 T v[UNR];
 #pragma unroll
@@ -328,6 +349,7 @@ struct BlockArgs {
     int64_t dim_up, dim_dn;
     int w_up, nblocks, nslab;
     double t;
+    double amp[4];
 };
 
 // Blocked slab pass.  Workgroup b works on slab s and row block k, with
@@ -338,7 +360,7 @@ struct BlockArgs {
 // The workgroup stages its block's slab segment in LDS; hops that stay inside
 // the block read LDS, the others read global memory.  Eight lanes cover one
 // 128-byte row segment with 16-byte accesses, so a wave updates eight rows.
-template <typename T, int MODE>
+template <typename T, int MODE, bool GT>
 __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *__restrict__ x, int64_t ldx,
                                                          T *__restrict__ y, int64_t ldy, double alpha,
                                                          const double *__restrict__ coef,
@@ -365,7 +387,8 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
         alpha = coef[0];
     else if (MODE == HV_FUSED)
         alpha = coef[1];
-    const T a_s = (T)alpha, tp = (T)p.t, tm = (T)(-p.t);
+    const T a_s = (T)alpha, tp = (T)p.t;
+    const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwave = blockDim.x >> 6;
     const int xcd = blockIdx.x & 7;
@@ -415,8 +438,9 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
                 for (int u = 0; u < 8; u++) {
                     const bool live = k0 + u < ni;
                     const uint32_t e = er[live ? k0 + u : 0];
-                    li[u] = live ? (int)(e & 0x7fffffffu) : rl;
-                    cf[u] = live ? ((e >> 31) ? tp : tm) : (T)0;
+                    li[u] = live ? (int)(e & (GT ? kGtRowMask : 0x7fffffffu)) : rl;
+                    const T ap = GT ? class_amp(am, (e >> 24) & 3u) : tp;
+                    cf[u] = live ? ((e >> 31) ? ap : -ap) : (T)0;
                 }
                 vec v[8];
 #pragma unroll
@@ -433,8 +457,9 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
                 for (int u = 0; u < 8; u++) {
                     const bool live = k0 + u < ne;
                     const uint32_t e = er[live ? ni + k0 + u : 0];
-                    off[u] = (live ? (int64_t)(e & 0x7fffffffu) : r) * ldx;
-                    cf[u] = live ? ((e >> 31) ? tp : tm) : (T)0;
+                    off[u] = (live ? (int64_t)(e & (GT ? kGtRowMask : 0x7fffffffu)) : r) * ldx;
+                    const T ap = GT ? class_amp(am, (e >> 24) & 3u) : tp;
+                    cf[u] = live ? ((e >> 31) ? ap : -ap) : (T)0;
                 }
                 vec v[8];
 #pragma unroll
@@ -515,6 +540,7 @@ struct LineArgs {
     int64_t dim_up, dim_dn;
     int nblocks, nslab;
     double t;
+    double amp[4];
 };
 
 // Blocked slab pass, line layout (rows of at most 32 hops).  Same workgroup
@@ -528,7 +554,7 @@ struct LineArgs {
 // the only memory round trip of a step.  Internal hops are summed with the
 // sign applied by flipping the sign bit; -t (and alpha) multiply the sum once.
 // External rows are read four at a time.
-template <typename T, int MODE>
+template <typename T, int MODE, bool GT>
 __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__restrict__ x, int64_t ldx,
                                                         T *__restrict__ y, int64_t ldy, double alpha,
                                                         const double *__restrict__ coef,
@@ -554,7 +580,9 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
     else if (MODE == HV_FUSED)
         alpha = coef[1];
     // y += scale * sum_k (+-x_k): -t, times alpha in the Lanczos modes
-    const T scale = (MODE == HV_LANCZOS || MODE == HV_FUSED) ? (T)(alpha * -p.t) : (T)(-p.t);
+    const double mt = GT ? -1.0 : -p.t;
+    const T scale = (MODE == HV_LANCZOS || MODE == HV_FUSED) ? (T)(alpha * mt) : (T)mt;
+    const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwave = blockDim.x >> 6;
     const int xcd = blockIdx.x & 7;
@@ -651,15 +679,16 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
                         ev[u] = entry(k0 + u);
-                        const int li = k0 + u < ni ? (int)(ev[u] & 0x7fffffffu) : bs;
+                        const int li = k0 + u < ni ? (int)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) : bs;
                         v[u] = xs[li * 8 + q];
                     }
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
                         const uint32_t sg = ev[u] & 0x80000000u;
+                        const T ac = GT ? class_amp(am, (ev[u] >> 24) & 3u) : (T)1;
 #pragma unroll
                         for (int c = 0; c < EPL; c++)
-                            acc[c] += flip_sign(v[u][c], sg);
+                            acc[c] += GT ? ac * flip_sign(v[u][c], sg) : flip_sign(v[u][c], sg);
                     }
                 }
             }
@@ -672,16 +701,17 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                     for (int u = 0; u < XB; u++) {
                         const bool live = k0 + u < ne;
                         ev[u] = entry(31 - (k0 + u));
-                        const int64_t row = live ? (int64_t)(ev[u] & 0x7fffffffu) : r;
+                        const int64_t row = live ? (int64_t)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) : r;
                         v[u] = load_row(x + row * ldx, d);
                     }
 #pragma unroll
                     for (int u = 0; u < XB; u++) {
                         const bool live = k0 + u < ne;
                         const uint32_t sg = ev[u] & 0x80000000u;
+                        const T ac = GT ? class_amp(am, (ev[u] >> 24) & 3u) : (T)1;
 #pragma unroll
                         for (int c = 0; c < EPL; c++)
-                            acc[c] += live ? flip_sign(v[u][c], sg) : (T)0;
+                            acc[c] += live ? (GT ? ac * flip_sign(v[u][c], sg) : flip_sign(v[u][c], sg)) : (T)0;
                     }
                 }
             }
@@ -762,9 +792,9 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
     pl.elem_bytes = elem_bytes;
     const int64_t ddn = a.dim_dn;
     const size_t one_row = (size_t)(ddn + 1) * (size_t)elem_bytes;
-    // per-bond amplitudes run the one-pass kernel: the two-pass tables carry
-    // no amplitude class
-    pl.two_pass = one_row <= (size_t)kLdsBytes && !a.tcls;
+    // per-bond amplitudes with more than four classes run the one-pass kernel:
+    // the two-pass tables have room for two class bits
+    pl.two_pass = one_row <= (size_t)kLdsBytes && (!a.tcls || a.ncls <= kTwoPassClasses);
     if (!pl.two_pass) {
         pl.ld = ddn;
         pl.nparts = hv_blocks(a, elem_bytes);
@@ -813,7 +843,7 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes)
 }
 
 template <typename T, int RPB>
-static void launch_rows_rpb(const RowArgs &ra, bool g16, const HvPlan &pl, const T *x, int64_t ldx, T *y,
+static void launch_rows_rpb(const RowArgs &ra, bool g16, bool gt, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                             int64_t ldy, int mode, double alpha, const double *coef, hipStream_t s)
 {
     const size_t lds = row_lds<T, RPB>(ra.dim_dn);
@@ -823,24 +853,34 @@ static void launch_rows_rpb(const RowArgs &ra, bool g16, const HvPlan &pl, const
                            coef);
         HUB_HIP(hipGetLastError());
     };
-    if (g16) {
+    if (gt) {
+        // per-bond amplitudes use the 32-bit groups (the class sits above the offset)
         if (mode == HV_STORE)
-            go(hv_rows_kernel<T, RPB, HV_STORE, true>);
+            go(hv_rows_kernel<T, RPB, HV_STORE, false, true>);
         else if (mode == HV_LANCZOS)
-            go(hv_rows_kernel<T, RPB, HV_LANCZOS, true>);
+            go(hv_rows_kernel<T, RPB, HV_LANCZOS, false, true>);
         else if (mode == HV_FUSED)
-            go(hv_rows_kernel<T, RPB, HV_FUSED, true>);
+            go(hv_rows_kernel<T, RPB, HV_FUSED, false, true>);
         else
-            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, true>);
+            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false, true>);
+    } else if (g16) {
+        if (mode == HV_STORE)
+            go(hv_rows_kernel<T, RPB, HV_STORE, true, false>);
+        else if (mode == HV_LANCZOS)
+            go(hv_rows_kernel<T, RPB, HV_LANCZOS, true, false>);
+        else if (mode == HV_FUSED)
+            go(hv_rows_kernel<T, RPB, HV_FUSED, true, false>);
+        else
+            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, true, false>);
     } else {
         if (mode == HV_STORE)
-            go(hv_rows_kernel<T, RPB, HV_STORE, false>);
+            go(hv_rows_kernel<T, RPB, HV_STORE, false, false>);
         else if (mode == HV_LANCZOS)
-            go(hv_rows_kernel<T, RPB, HV_LANCZOS, false>);
+            go(hv_rows_kernel<T, RPB, HV_LANCZOS, false, false>);
         else if (mode == HV_FUSED)
-            go(hv_rows_kernel<T, RPB, HV_FUSED, false>);
+            go(hv_rows_kernel<T, RPB, HV_FUSED, false, false>);
         else
-            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false>);
+            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false, false>);
     }
 }
 
@@ -857,7 +897,10 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
         return pl.nparts;
     }
     RowArgs ra;
-    const bool g16 = a.dn_groups16 != nullptr;
+    const bool gt = a.tcls != nullptr;
+    const bool g16 = !gt && a.dn_groups16 != nullptr;
+    for (int c = 0; c < 4; c++)
+        ra.amp[c] = a.amp4[c];
     ra.groups = g16 ? a.dn_groups16 : (sizeof(T) == 8 ? a.dn_groups64 : a.dn_groups32);
     ra.nq = g16 ? a.dn_nq8 : a.dn_nq;
     ra.states_up = a.states_up;
@@ -870,11 +913,11 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     T *yr = mode == HV_RESIDUAL ? scratch : y;
     const int64_t ldyr = mode == HV_RESIDUAL ? lds_ : ldy;
     if (pl.rows_rpb == 3)
-        launch_rows_rpb<T, 3>(ra, g16, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+        launch_rows_rpb<T, 3>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else if (pl.rows_rpb == 2)
-        launch_rows_rpb<T, 2>(ra, g16, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+        launch_rows_rpb<T, 2>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else
-        launch_rows_rpb<T, 1>(ra, g16, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+        launch_rows_rpb<T, 1>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
 
     const int64_t slw = 128 / (int64_t)sizeof(T);
     if (pl.blk_grid > 0 && ldx % slw == 0 && ldyr % slw == 0) {
@@ -889,6 +932,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
         ba.nblocks = a.up_nblocks;
         ba.nslab = pl.blk_nslab;
         ba.t = a.t;
+        for (int c = 0; c < 4; c++)
+            ba.amp[c] = a.amp4[c];
         auto gob = [&](auto kern) {
             if (pl.blk_lds > 64 * 1024)
                 HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -907,6 +952,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             la.nblocks = a.up_nblocks;
             la.nslab = pl.blk_nslab;
             la.t = a.t;
+            for (int c = 0; c < 4; c++)
+                la.amp[c] = a.amp4[c];
             auto gol = [&](auto kern) {
                 if (pl.blk_lds > 64 * 1024)
                     HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -916,23 +963,23 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                 HUB_HIP(hipGetLastError());
             };
             if (mode == HV_STORE)
-                gol(hv_lines_kernel<T, HV_STORE>);
+                gt ? gol(hv_lines_kernel<T, HV_STORE, true>) : gol(hv_lines_kernel<T, HV_STORE, false>);
             else if (mode == HV_LANCZOS)
-                gol(hv_lines_kernel<T, HV_LANCZOS>);
+                gt ? gol(hv_lines_kernel<T, HV_LANCZOS, true>) : gol(hv_lines_kernel<T, HV_LANCZOS, false>);
             else if (mode == HV_FUSED)
-                gol(hv_lines_kernel<T, HV_FUSED>);
+                gt ? gol(hv_lines_kernel<T, HV_FUSED, true>) : gol(hv_lines_kernel<T, HV_FUSED, false>);
             else
-                gol(hv_lines_kernel<T, HV_RESIDUAL>);
+                gt ? gol(hv_lines_kernel<T, HV_RESIDUAL, true>) : gol(hv_lines_kernel<T, HV_RESIDUAL, false>);
             return pl.blk_grid;
         }
         if (mode == HV_STORE)
-            gob(hv_blocks_kernel<T, HV_STORE>);
+            gt ? gob(hv_blocks_kernel<T, HV_STORE, true>) : gob(hv_blocks_kernel<T, HV_STORE, false>);
         else if (mode == HV_LANCZOS)
-            gob(hv_blocks_kernel<T, HV_LANCZOS>);
+            gt ? gob(hv_blocks_kernel<T, HV_LANCZOS, true>) : gob(hv_blocks_kernel<T, HV_LANCZOS, false>);
         else if (mode == HV_FUSED)
-            gob(hv_blocks_kernel<T, HV_FUSED>);
+            gt ? gob(hv_blocks_kernel<T, HV_FUSED, true>) : gob(hv_blocks_kernel<T, HV_FUSED, false>);
         else
-            gob(hv_blocks_kernel<T, HV_RESIDUAL>);
+            gt ? gob(hv_blocks_kernel<T, HV_RESIDUAL, true>) : gob(hv_blocks_kernel<T, HV_RESIDUAL, false>);
         return pl.blk_grid;
     }
     if (mode == HV_FUSED)
@@ -947,6 +994,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     sa.rows_per_wg = pl.slab_rw;
     sa.nslab = pl.nslab;
     sa.t = a.t;
+    for (int c = 0; c < 4; c++)
+        sa.amp[c] = a.amp4[c];
     auto go = [&](auto kern) {
         if (pl.slab_lds > 64 * 1024)
             HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -956,11 +1005,11 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
         HUB_HIP(hipGetLastError());
     };
     if (mode == HV_STORE)
-        go(hv_slabs_kernel<T, HV_STORE>);
+        gt ? go(hv_slabs_kernel<T, HV_STORE, true>) : go(hv_slabs_kernel<T, HV_STORE, false>);
     else if (mode == HV_LANCZOS)
-        go(hv_slabs_kernel<T, HV_LANCZOS>);
+        gt ? go(hv_slabs_kernel<T, HV_LANCZOS, true>) : go(hv_slabs_kernel<T, HV_LANCZOS, false>);
     else
-        go(hv_slabs_kernel<T, HV_RESIDUAL>);
+        gt ? go(hv_slabs_kernel<T, HV_RESIDUAL, true>) : go(hv_slabs_kernel<T, HV_RESIDUAL, false>);
     return pl.slab_grid;
 }
 

@@ -45,6 +45,9 @@ inline uint32_t pack_entry_class(int32_t col, int8_t sgn, int cls)
 }
 constexpr uint32_t kClassColMask = 0x00FFFFFFu;
 constexpr int kMaxAmpClasses = 127;
+// per-bond handles with at most this many classes also get the two-pass tables
+// (two class bits in the row-pass groups and the up-spin entries)
+constexpr int kTwoPassClasses = 4;
 
 struct DeviceTables {
     uint32_t *states_up = nullptr, *states_dn = nullptr;
@@ -118,6 +121,7 @@ struct HvArgs {
     // up_rows / dn_cols entries (NULL: every hop has amplitude t)
     const double *tcls = nullptr;
     int ncls = 0;
+    double amp4[4] = {0.0, 0.0, 0.0, 0.0};  // the classes, for the two-pass kernels (ncls <= kTwoPassClasses)
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
     const uint4 *dn_groups64, *dn_groups32;

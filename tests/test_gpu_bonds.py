@@ -5,8 +5,10 @@ H.v: the same bound as the one-amplitude case (a sum of at most 1 + w_up + w_dn
 terms in a different order): max|y - y_ref| <= 1e-13 max|y_ref| in FP64 and
 the FP32 bound n u sum|terms| in mixed precision.  E0: 1e-10 relative (FP64),
 1e-6 (mixed), against the oracle's Lanczos from the same start vector.  The
-per-bond handle runs the one-pass kernel, with its row staged in LDS and
-(rows wider than LDS) not staged; both are covered.
+per-bond handle with at most four amplitude classes runs the two-pass kernels
+(class bits in the row-pass groups and the up-spin entries), one with more
+runs the one-pass kernel, with its row staged in LDS and (rows wider than LDS)
+not staged; all of these are covered.
 """
 import numpy as np
 import pytest
@@ -45,7 +47,25 @@ CASES = [
     ("chain10_ssh", 10, workload.chain(10), [1.0 if i % 2 == 0 else 0.4 for i in range(9)], 5, 5, 2.0),
     # rows of 48,620 elements (18 sites, 9 down): wider than LDS, the kernel reads x directly
     ("ring18_1u9d", 18, workload.ring(18), np.random.default_rng(2).uniform(0.5, 1.5, 18), 1, 9, 4.0),
+    # four amplitude classes (the most the two-pass kernels take) and five (one-pass)
+    ("ring10_4classes", 10, workload.ring(10), [0.5, 0.8, -1.1, 1.4] * 2 + [0.5, 0.8], 4, 4, 3.0),
+    ("ring10_5classes", 10, workload.ring(10), [0.5, 0.8, -1.1, 1.4, 0.9] * 2, 4, 4, 3.0),
 ]
+
+
+def _two_pass(h):
+    """The two-pass kernels run with padded rows (ld_pref a multiple of 64 above
+    dim_dn), the one-pass kernel with dense ones (ld_pref = dim_dn)."""
+    return hb.hubbard_info(h)["ld_pref"] != h.dim_dn
+
+
+def test_bonds_kernel_choice():
+    """Up to four amplitude classes take the two-pass kernels, more take the one-pass kernel."""
+    want = {"ring8_random": False, "torus3x4_tprime": True, "chain10_ssh": True, "ring18_1u9d": False,
+            "ring10_4classes": True, "ring10_5classes": False}
+    for name, sites, edges, amps, nu, nd, U in CASES:
+        h = hb.hubbard_build_bonds(sites, edges, amps, nu, nd, U)
+        assert _two_pass(h) == want[name], name
 
 
 @pytest.mark.parametrize("name,sites,edges,amps,nu,nd,U", CASES, ids=[c[0] for c in CASES])
