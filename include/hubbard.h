@@ -124,11 +124,11 @@ int hubbard_build(int sites, const int32_t *edges, int n_edges, int n_up, int n_
  * finite values (NULL only when n_edges = 0).  If all t[k] are equal the
  * handle is exactly the hubbard_build one.  Otherwise the amplitudes are
  * grouped into classes of equal value (at most 127) whose index each table
- * entry carries; such a handle runs the one-pass H.v kernel for every call
- * (the two-pass kernels take one amplitude), runs unbatched in
- * hubbard_lanczos_batch, reports t = NaN in hubbard_info, and takes only
- * dense rows in hubbard_apply_ld (ld = dim_dn, which hubbard_info reports as
- * ld_pref).
+ * entry carries.  With at most four classes the two-pass H.v kernels run (the
+ * class takes two bits of their entries); with more, the one-pass kernel runs
+ * every call and hubbard_apply_ld takes only dense rows (ld = dim_dn, which
+ * hubbard_info then reports as ld_pref).  Such a handle runs unbatched in
+ * hubbard_lanczos_batch and reports t = NaN in hubbard_info.
  * Errors: as hubbard_build; EINVAL also for more than 127 distinct
  * amplitudes or a non-finite one; ERANGE also when non-uniform amplitudes meet
  * a spin dimension of 2^24 or more (the column must fit 24 bits beside the
@@ -175,8 +175,9 @@ int hubbard_apply(hubbard_h h, const void *x, void *y);
  * bytes (and buffers aligned to 128 bytes) select the blocked up-spin pass,
  * which works on one cache line of every row at a time; other strides take a
  * slower pass.  Where the one-pass kernel runs (rows too wide for LDS, or a
- * handle with per-bond amplitudes) ld_pref is dim_dn and only dense rows
- * (ldx = ldy = dim_dn) are accepted: other strides return EINVAL. */
+ * handle with more than four distinct per-bond amplitudes) ld_pref is dim_dn
+ * and only dense rows (ldx = ldy = dim_dn) are accepted: other strides return
+ * EINVAL. */
 int hubbard_apply_ld(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t ldy);
 
 /* Lanczos ground state (Sec. 2.2, Alg. 1, two-vector form): iterates until
