@@ -531,12 +531,16 @@ def _kernel_family(name):
         if fam in name:
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""
+            gt = ""
             if fam in ("hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel"):
                 targs = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "").split(",")
                 k = 2 if fam == "hv_rows_kernel" else 1
                 mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused"}.get(
                     targs[k] if len(targs) > k else "", "")
-            return " ".join(x for x in (fam, prec, mode) if x)
+                # the per-bond variant: last template argument (5 for the row pass, 3 for the others)
+                if len(targs) == (5 if fam == "hv_rows_kernel" else 3) and targs[-1] == "true":
+                    gt = "per-bond"
+            return " ".join(x for x in (fam, prec, mode, gt) if x)
     return name[:60]
 
 
