@@ -506,8 +506,11 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     if (resident) {
         const size_t vb = sizeof(T) * (size_t)npad;
         if (pool.vb != vb) {
-            HUB_HIP(hipDeviceSynchronize());
-            pool.chunks.clear();
+            // slots of another size: the work that used them ran on this stream
+            if (!pool.chunks.empty()) {
+                HUB_HIP(hipStreamSynchronize(s));
+                pool.chunks.clear();
+            }
             pool.vb = vb;
         }
         size_t fr = 0, tot = 0;
