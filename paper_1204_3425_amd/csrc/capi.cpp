@@ -177,19 +177,22 @@ static void upload_blocked_up(hubbard *h, size_t &total)
         nint[(size_t)r] = (uint16_t)ni;
         next[(size_t)r] = (uint16_t)ne;
     }
-    if (up.width <= 32) {
-        std::vector<uint32_t> line((size_t)du * 32, 0u), cnt((size_t)du);
+    if (up.width <= 64) {
+        // one 128-byte line of 32 slots per row, or two (64 slots) for rows of 33 to 64 hops
+        const int W = up.width <= 32 ? 32 : 64;
+        std::vector<uint32_t> line((size_t)du * (size_t)W, 0u), cnt((size_t)du);
         for (int64_t r = 0; r < du; r++) {
             const size_t o = (size_t)r * (size_t)w;
             const int ni = nint[(size_t)r], ne = next[(size_t)r];
             for (int k = 0; k < ni; k++)
-                line[(size_t)r * 32 + (size_t)k] = ent[o + (size_t)k];
+                line[(size_t)r * W + (size_t)k] = ent[o + (size_t)k];
             for (int k = 0; k < ne; k++)
-                line[(size_t)r * 32 + 31 - (size_t)k] = ent[o + (size_t)(ni + k)];
+                line[(size_t)r * W + (size_t)(W - 1 - k)] = ent[o + (size_t)(ni + k)];
             cnt[(size_t)r] = (uint32_t)ni | ((uint32_t)ne << 16);
         }
         d.up_line = upload<uint32_t>(line.data(), line.size() * 4, total);
         d.up_cnt = upload<uint32_t>(cnt.data(), cnt.size() * 4, total);
+        d.up_line_w = W;
     }
     d.up_blk = upload<uint32_t>(ent.data(), ent.size() * 4, total);
     d.up_nint = upload<uint16_t>(nint.data(), nint.size() * 2, total);
@@ -316,6 +319,7 @@ static HvArgs hv_args(const hubbard *h)
     a.up_nblocks = h->dev.up_nblocks;
     a.up_max_block = h->dev.up_max_block;
     a.up_line = h->dev.up_line;
+    a.up_line_w = h->dev.up_line_w;
     a.up_cnt = h->dev.up_cnt;
     a.dim_up = h->up.dim;
     a.dim_dn = h->dn.dim;

@@ -543,7 +543,7 @@ struct LineArgs {
     double amp[4];
 };
 
-// Blocked slab pass, line layout (rows of at most 32 hops).  Same workgroup
+// Blocked slab pass, line layout (rows of at most 64 hops).  Same workgroup
 // numbering and LDS staging as hv_blocks_kernel, plus a zero row after the
 // block that padding hops point at.  A row's entries are one 128-byte line
 // (internal hops from the front, external from the back): each of the eight
@@ -554,7 +554,9 @@ struct LineArgs {
 // the only memory round trip of a step.  Internal hops are summed with the
 // sign applied by flipping the sign bit; -t (and alpha) multiply the sum once.
 // External rows are read four at a time.
-template <typename T, int MODE, bool GT>
+// W = 32: one 128-byte line per row; W = 64 (rows of 33 to 64 hops): two lines,
+// lane q of a row group holding slots 4q..4q+3 of each.
+template <typename T, int MODE, bool GT, int W>
 __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__restrict__ x, int64_t ldx,
                                                         T *__restrict__ y, int64_t ldy, double alpha,
                                                         const double *__restrict__ coef,
@@ -630,13 +632,19 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
         };
         // Lane q of a row group holds slots 4q..4q+3 of the row's line; entry
         // k reaches every lane of the group by a permute within the group.
-        uint4 Em = make_uint4(0u, 0u, 0u, 0u);
+        constexpr int NL = W / 32;  // 128-byte lines per row
+        uint4 Em[NL];
+#pragma unroll
+        for (int h = 0; h < NL; h++)
+            Em[h] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t C = 0;
         vec prev = (vec)(T)0;
         int rb = wave * 8;
         if (rb < bs) {
             const int64_t r = b0 + min(rb + sub, bs - 1);
-            Em = p.line[r * 8 + q];
+#pragma unroll
+            for (int h = 0; h < NL; h++)
+                Em[h] = p.line[(r * NL + h) * 8 + q];
             C = p.cnt[r];
             if (rb + sub < bs)
                 prev = load_prev(r);
@@ -647,13 +655,18 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
             const int64_t r = b0 + rl;
             T *yp = y + r * ldy + d;
             // the next row group's entries, counts and running output, a step ahead
-            uint4 En = Em;
+            uint4 En[NL];
+#pragma unroll
+            for (int h = 0; h < NL; h++)
+                En[h] = Em[h];
             uint32_t Cn = 0;
             vec prevn = (vec)(T)0;
             const int rbn = rb + nwave * 8;
             if (rbn < bs) {
                 const int64_t rn = b0 + min(rbn + sub, bs - 1);
-                En = p.line[rn * 8 + q];
+#pragma unroll
+                for (int h = 0; h < NL; h++)
+                    En[h] = p.line[(rn * NL + h) * 8 + q];
                 Cn = p.cnt[rn];
                 if (rbn + sub < bs)
                     prevn = load_prev(rn);
@@ -667,12 +680,13 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
             nim = __builtin_amdgcn_readfirstlane(nim);
             nem = __builtin_amdgcn_readfirstlane(nem);
             auto entry = [&](int k) -> uint32_t {
-                const uint32_t c = (k & 3) == 0 ? Em.x : (k & 3) == 1 ? Em.y : (k & 3) == 2 ? Em.z : Em.w;
-                return (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + (k >> 2)) << 2, (int)c);
+                const uint4 &E = Em[k >> 5];
+                const uint32_t c = (k & 3) == 0 ? E.x : (k & 3) == 1 ? E.y : (k & 3) == 2 ? E.z : E.w;
+                return (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + ((k & 31) >> 2)) << 2, (int)c);
             };
             vec acc = (vec)(T)0;
 #pragma unroll
-            for (int k0 = 0; k0 < 32; k0 += 8) {
+            for (int k0 = 0; k0 < W; k0 += 8) {
                 if (k0 < nim) {
                     vec v[8];
                     uint32_t ev[8];
@@ -693,14 +707,14 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                 }
             }
 #pragma unroll
-            for (int k0 = 0; k0 < 32; k0 += XB) {
+            for (int k0 = 0; k0 < W; k0 += XB) {
                 if (k0 < nem) {
                     vec v[XB];
                     uint32_t ev[XB];
 #pragma unroll
                     for (int u = 0; u < XB; u++) {
                         const bool live = k0 + u < ne;
-                        ev[u] = entry(31 - (k0 + u));
+                        ev[u] = entry(W - 1 - (k0 + u));
                         const int64_t row = live ? (int64_t)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) : r;
                         v[u] = load_row(x + row * ldx, d);
                     }
@@ -744,7 +758,9 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                     }
                 }
             }
-            Em = En;
+#pragma unroll
+            for (int h = 0; h < NL; h++)
+                Em[h] = En[h];
             C = Cn;
             prev = prevn;
         }
@@ -952,6 +968,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             la.nblocks = a.up_nblocks;
             la.nslab = pl.blk_nslab;
             la.t = a.t;
+            const bool w64 = a.up_line_w == 64;
             for (int c = 0; c < 4; c++)
                 la.amp[c] = a.amp4[c];
             auto gol = [&](auto kern) {
@@ -963,13 +980,17 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                 HUB_HIP(hipGetLastError());
             };
             if (mode == HV_STORE)
-                gt ? gol(hv_lines_kernel<T, HV_STORE, true>) : gol(hv_lines_kernel<T, HV_STORE, false>);
+                w64 ? (gt ? gol(hv_lines_kernel<T, HV_STORE, true, 64>) : gol(hv_lines_kernel<T, HV_STORE, false, 64>))
+                    : (gt ? gol(hv_lines_kernel<T, HV_STORE, true, 32>) : gol(hv_lines_kernel<T, HV_STORE, false, 32>));
             else if (mode == HV_LANCZOS)
-                gt ? gol(hv_lines_kernel<T, HV_LANCZOS, true>) : gol(hv_lines_kernel<T, HV_LANCZOS, false>);
+                w64 ? (gt ? gol(hv_lines_kernel<T, HV_LANCZOS, true, 64>) : gol(hv_lines_kernel<T, HV_LANCZOS, false, 64>))
+                    : (gt ? gol(hv_lines_kernel<T, HV_LANCZOS, true, 32>) : gol(hv_lines_kernel<T, HV_LANCZOS, false, 32>));
             else if (mode == HV_FUSED)
-                gt ? gol(hv_lines_kernel<T, HV_FUSED, true>) : gol(hv_lines_kernel<T, HV_FUSED, false>);
+                w64 ? (gt ? gol(hv_lines_kernel<T, HV_FUSED, true, 64>) : gol(hv_lines_kernel<T, HV_FUSED, false, 64>))
+                    : (gt ? gol(hv_lines_kernel<T, HV_FUSED, true, 32>) : gol(hv_lines_kernel<T, HV_FUSED, false, 32>));
             else
-                gt ? gol(hv_lines_kernel<T, HV_RESIDUAL, true>) : gol(hv_lines_kernel<T, HV_RESIDUAL, false>);
+                w64 ? (gt ? gol(hv_lines_kernel<T, HV_RESIDUAL, true, 64>) : gol(hv_lines_kernel<T, HV_RESIDUAL, false, 64>))
+                    : (gt ? gol(hv_lines_kernel<T, HV_RESIDUAL, true, 32>) : gol(hv_lines_kernel<T, HV_RESIDUAL, false, 32>));
             return pl.blk_grid;
         }
         if (mode == HV_STORE)

@@ -77,6 +77,7 @@ struct DeviceTables {
     uint32_t *up_line = nullptr, *up_cnt = nullptr;
     size_t bytes = 0;
     double *tcls = nullptr;  // amplitude of each class (per-bond amplitudes only)
+    int up_line_w = 32;      // slots per row of up_line (32 or 64)
 };
 
 }  // namespace hub
@@ -122,6 +123,7 @@ struct HvArgs {
     const double *tcls = nullptr;
     int ncls = 0;
     double amp4[4] = {0.0, 0.0, 0.0, 0.0};  // the classes, for the two-pass kernels (ncls <= kTwoPassClasses)
+    int up_line_w = 32;  // slots per row of up_line: 32 (one 128-byte line) or 64 (two)
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
     const uint4 *dn_groups64, *dn_groups32;
@@ -133,7 +135,7 @@ struct HvArgs {
     const uint16_t *up_nint, *up_next;
     const int32_t *up_bstart;
     int up_nblocks, up_max_block;
-    const uint32_t *up_line, *up_cnt;  // null when a row has more than 32 hops
+    const uint32_t *up_line, *up_cnt;  // null when a row has more than 64 hops
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
     double t, U;

@@ -143,3 +143,35 @@ def test_bonds_through_lowest_states_propagate_and_batch():
     hu = hb.hubbard_build(8, workload.ring(8), 3, 3, 1.0, 2.0)
     batch = hb.hubbard_lanczos_batch([h, hu], tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seeds=[7, 7])
     assert batch[0]["E0"] == single["E0"]
+
+
+@pytest.mark.parametrize("per_bond", [False, True], ids=["one_amplitude", "per_bond"])
+def test_rows_of_33_to_64_hops(per_bond):
+    """The 4x4 lattice with diagonal bonds, 8 up + 2 down (dim 1.54M): up rows of
+    up to 48 hops take the two-line (64-slot) layout of the up-spin pass.  H.v in
+    FP64 and FP32 against the oracle, and the first 20 Lanczos coefficients of the
+    fused step (sectors of 65,536 states and more) against the oracle's from the
+    same start vector."""
+    edges, amps = workload.torus_tprime(4, 4, 1.0, -0.3 if per_bond else 1.0)
+    U = 5.0
+    h = (hb.hubbard_build_bonds(16, edges, amps, 8, 2, U) if per_bond
+         else hb.hubbard_build(16, edges, 8, 2, 1.0, U))
+    info = hb.hubbard_info(h)
+    assert 32 < info["w_up"] <= 64 and _two_pass(h)
+    m = oracle.Model(16, edges, 8, 2, amps if per_bond else 1.0, U)
+    x = workload.random_vector(m.dim, workload.BASE_SEED)
+    ref = m.apply(x)
+    for precision, dt in ((hb.HUBBARD_FP64, torch.float64), (hb.HUBBARD_MIXED, torch.float32)):
+        hb.hubbard_set_precision(h, precision)
+        xd = torch.from_numpy(x).to(DEV, dt)
+        yd = torch.empty_like(xd)
+        hb.hubbard_apply(h, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.double().cpu().numpy()
+        tol = 1e-13 if precision == hb.HUBBARD_FP64 else 64 * (1 + info["w_up"] + info["w_dn"]) * 2.0 ** -24
+        assert np.abs(y - ref).max() <= tol * np.abs(ref).max(), precision
+    f1 = oracle.start_vector(workload.BASE_SEED, m.dim)
+    ro = m.lanczos(f1, tol=1e-300, max_iter=20)
+    r = hb.hubbard_lanczos_ex(h, tol=-1.0, max_iter=20, precision=hb.HUBBARD_FP64, seed=workload.BASE_SEED)
+    assert np.allclose(r["a"], ro["a"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(r["b"], ro["b"], rtol=1e-10, atol=1e-12)
