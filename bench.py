@@ -537,9 +537,13 @@ def _kernel_family(name):
                 k = 2 if fam == "hv_rows_kernel" else 1
                 mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused"}.get(
                     targs[k] if len(targs) > k else "", "")
-                # the per-bond variant: last template argument (5 for the row pass, 3 for the others)
-                if len(targs) == (5 if fam == "hv_rows_kernel" else 3) and targs[-1] == "true":
+                # the per-bond variant: template argument 4 of the row pass, 2 of the others; the line
+                # pass also names its line width (32 or 64 slots)
+                g = 4 if fam == "hv_rows_kernel" else 2
+                if len(targs) > g and targs[g] == "true":
                     gt = "per-bond"
+                if fam == "hv_lines_kernel" and len(targs) > 3 and targs[3] == "64":
+                    gt = (gt + " 64-slot").strip()
             return " ".join(x for x in (fam, prec, mode, gt) if x)
     return name[:60]
 
