@@ -540,7 +540,7 @@ def _kernel_family(name):
                 # the per-bond variant: template argument 4 of the row pass, 2 of the others; the line
                 # pass also names its line width (32 or 64 slots)
                 g = 4 if fam == "hv_rows_kernel" else 2
-                if len(targs) > g and targs[g] == "true":
+                if len(targs) > g and targs[g] not in ("false", "0"):
                     gt = "per-bond"
                 if fam == "hv_lines_kernel" and len(targs) > 3 and targs[3] == "64":
                     gt = (gt + " 64-slot").strip()
