@@ -149,9 +149,11 @@ def test_bonds_through_lowest_states_propagate_and_batch():
 def test_rows_of_33_to_64_hops(per_bond):
     """The 4x4 lattice with diagonal bonds, 8 up + 2 down (dim 1.54M): up rows of
     up to 48 hops take the two-line (64-slot) layout of the up-spin pass.  H.v in
-    FP64 and FP32 against the oracle, and the first 20 Lanczos coefficients of the
+    FP64 and FP32 against the oracle, the first 20 Lanczos coefficients of the
     fused step (sectors of 65,536 states and more) against the oracle's from the
-    same start vector."""
+    same start vector in FP64 and mixed precision, and the FP64 residual that a
+    converged solve reports (the residual epilogue of the same kernels) against
+    ||H psi - E0 psi|| from the oracle's H on the returned psi."""
     edges, amps = workload.torus_tprime(4, 4, 1.0, -0.3 if per_bond else 1.0)
     U = 5.0
     h = (hb.hubbard_build_bonds(16, edges, amps, 8, 2, U) if per_bond
@@ -175,3 +177,14 @@ def test_rows_of_33_to_64_hops(per_bond):
     r = hb.hubbard_lanczos_ex(h, tol=-1.0, max_iter=20, precision=hb.HUBBARD_FP64, seed=workload.BASE_SEED)
     assert np.allclose(r["a"], ro["a"], rtol=1e-12, atol=1e-12)
     assert np.allclose(r["b"], ro["b"], rtol=1e-10, atol=1e-12)
+    # FP32 vectors: coefficients within a few FP32 ulps of the H.v sums, grown over 20 steps
+    rm = hb.hubbard_lanczos_ex(h, tol=-1.0, max_iter=20, precision=hb.HUBBARD_MIXED, seed=workload.BASE_SEED)
+    assert np.allclose(rm["a"], ro["a"], rtol=1e-4, atol=1e-4)
+    psi = torch.zeros(h.dim, dtype=torch.float64, device=DEV)
+    rs = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=600, precision=hb.HUBBARD_FP64, seed=workload.BASE_SEED,
+                               psi=psi)
+    v = psi.cpu().numpy()
+    res = np.linalg.norm(m.apply(v) - rs["E0"] * v) / np.linalg.norm(v)
+    _say("residual", rs["residual"], "oracle", res, "steps", rs["n_iter"])
+    assert 0.0 <= rs["residual"] <= 1e-4
+    assert abs(rs["residual"] - res) <= 1e-9 + 1e-6 * res
