@@ -715,8 +715,10 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                     for (int u = 0; u < XB; u++) {
                         const bool live = k0 + u < ne;
                         ev[u] = entry(W - 1 - (k0 + u));
-                        const int64_t row = live ? (int64_t)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) : r;
-                        v[u] = load_row(x + row * ldx, d);
+                        // slots past this row's external count issue no load
+                        v[u] = (vec)(T)0;
+                        if (live)
+                            v[u] = load_row(x + (int64_t)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) * ldx, d);
                     }
 #pragma unroll
                     for (int u = 0; u < XB; u++) {
