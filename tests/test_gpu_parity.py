@@ -116,8 +116,11 @@ PADDED_CASES = [
     # more than 1024 up configurations: several row blocks, hops inside and across blocks
     workload.problem("ring14", 14, workload.ring(14), 7, 7, 1.0, 4.0),
     workload.problem("torus3x4_t07", 12, workload.torus(3, 4), 6, 5, 0.7, 3.0),
-    # every pair of 12 sites bonded: up rows of 36 hops (more than one 32-slot line)
+    # every pair of 12 sites bonded: up rows of 36 hops (the two-line, 64-slot layout)
     workload.problem("complete12", 12, [(i, j) for i in range(12) for j in range(i + 1, 12)], 6, 2, 1.0, 2.0),
+    # every pair of 17 sites bonded, 8 up: up rows of 72 hops, more than the line
+    # layouts hold (the variable-width blocked pass)
+    workload.problem("complete17_8u1d", 17, [(i, j) for i in range(17) for j in range(i + 1, 17)], 8, 1, 1.0, 3.0),
     workload.problem("chain13_ragged", 13, workload.chain(13), 7, 3, 1.0, 5.0),
 ]
 
@@ -373,6 +376,22 @@ def test_lanczos_wide_up_rows():
     got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, 1e-12, 300)
     assert got["E0"] == pytest.approx(ref["E0"], rel=1e-10)
     assert np.allclose(got["a"][:20], ref["a"][:20], rtol=1e-12, atol=1e-13)
+
+
+def test_lanczos_up_rows_over_64_hops():
+    """Up rows of up to 72 hops (17 sites, each pair bonded with probability 0.9,
+    seeded: 128 bonds; 8 up + 1 down, 413,270 states): the fused step on the
+    variable-width blocked pass for 20 steps.  (The complete graph has so few
+    distinct energies that its Krylov space ends after about ten steps.)"""
+    g = np.random.default_rng(17)
+    edges = [(i, j) for i in range(17) for j in range(i + 1, 17) if g.random() < 0.9]
+    p = workload.problem("dense17_8u1d", 17, edges, 8, 1, 1.0, 3.0)
+    h = _build(p)
+    assert hb.hubbard_info(h)["w_up"] > 64
+    ref = _oracle(p).lanczos(oracle.start_vector(p.seed, p.dim), tol=1e-300, max_iter=20)
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, -1.0, 20)
+    assert np.allclose(got["a"], ref["a"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(got["b"], ref["b"], rtol=1e-10, atol=1e-12)
 
 
 def test_lanczos_large_sector_breakdown():
