@@ -188,3 +188,40 @@ def test_rows_of_33_to_64_hops(per_bond):
     _say("residual", rs["residual"], "oracle", res, "steps", rs["n_iter"])
     assert 0.0 <= rs["residual"] <= 1e-4
     assert abs(rs["residual"] - res) <= 1e-9 + 1e-6 * res
+
+
+def test_per_bond_up_rows_over_64_hops():
+    """Two amplitude classes on up rows of up to 72 hops (17 sites, each pair
+    bonded with probability 0.9, seeded; 8 up + 1 down, 413,270 states): the
+    per-bond variant of the variable-width blocked pass.  H.v in FP64 and FP32
+    against the oracle's per-bond model, and 20 Lanczos steps of the fused step
+    against the oracle's from the same start vector."""
+    g = np.random.default_rng(17)
+    edges = [(i, j) for i in range(17) for j in range(i + 1, 17) if g.random() < 0.9]
+    amps = [1.0 if k % 3 else 0.55 for k in range(len(edges))]
+    U = 3.0
+    h = hb.hubbard_build_bonds(17, edges, amps, 8, 1, U)
+    info = hb.hubbard_info(h)
+    assert info["w_up"] > 64 and _two_pass(h)
+    m = oracle.Model(17, edges, 8, 1, amps, U)
+    x = workload.random_vector(m.dim, workload.BASE_SEED + 1)
+    ref = m.apply(x)
+    for precision, dt in ((hb.HUBBARD_FP64, torch.float64), (hb.HUBBARD_MIXED, torch.float32)):
+        hb.hubbard_set_precision(h, precision)
+        xd = torch.from_numpy(x).to(DEV, dt)
+        yd = torch.empty_like(xd)
+        hb.hubbard_apply(h, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.double().cpu().numpy()
+        if precision == hb.HUBBARD_FP64:
+            assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+        else:
+            # the FP32 bound of the other per-bond cases: n u sum|terms|
+            w = info["w_up"] + info["w_dn"]
+            xf = xd.double().cpu().numpy()
+            S = (max(amps) * w + U * 1) * np.abs(xf).max()
+            assert np.abs(y - m.apply(xf)).max() <= (1 + w) * 2.0 ** -24 * S
+    ro = m.lanczos(oracle.start_vector(workload.BASE_SEED, m.dim), tol=1e-300, max_iter=20)
+    r = hb.hubbard_lanczos_ex(h, tol=-1.0, max_iter=20, precision=hb.HUBBARD_FP64, seed=workload.BASE_SEED)
+    assert np.allclose(r["a"], ro["a"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(r["b"], ro["b"], rtol=1e-10, atol=1e-12)
