@@ -463,8 +463,12 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
                 }
                 vec v[8];
 #pragma unroll
-                for (int u = 0; u < 8; u++)
-                    v[u] = load_row(x + off[u], d);
+                for (int u = 0; u < 8; u++) {
+                    // slots past this row's external count issue no load
+                    v[u] = (vec)(T)0;
+                    if (k0 + u < ne)
+                        v[u] = load_row(x + off[u], d);
+                }
 #pragma unroll
                 for (int u = 0; u < 8; u++)
                     acc += cf[u] * v[u];
