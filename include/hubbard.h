@@ -343,6 +343,7 @@ typedef struct {
     uint64_t budget, reserved, peak_reserved;   /* bytes */
     uint64_t submitted, admitted, completed, rejected, pending;
     int32_t max_active_batch, slots_used;
+    uint64_t solo_runs;   /* requests run by the executor for large sectors (one at a time, own stream) */
 } hubbard_server_stats_t;
 
 /* Creates a server with an HBM budget (bytes, > 0) and a slot limit (>= 1). */

@@ -480,9 +480,43 @@ typedef struct {
     double rayleigh;  /* <psi|H|psi>, when psi was requested */
 } orc_result;
 
-/* Alg. 1.  f1 (length dim, unit norm) is the start vector.  a[j-1] = a_j and
+/* The tridiagonal T of eq. Tmatrix (Sec. 2.2) comes from the three-term
+ * relation that orthonormal Krylov vectors of a symmetric H obey,
+ *     H f_j = b_j f_{j-1} + a_j f_j + b_{j+1} f_{j+1}   (f_0 = 0, b_1 = 0).
+ * Given f_{j-1}, f_j and b_j, this finds the next coefficients: a_j is the
+ * component along f_j of what H f_j leaves after its f_{j-1} part is taken
+ * away, and b_{j+1} the length of the rest, which is left in r (it is
+ * b_{j+1} f_{j+1}).  The paper's Alg. 1 is this relation run from a random
+ * unit f_1 without re-orthogonalisation, as here. */
+static void next_coefficients(const orc_model *m, const double *f_prev, const double *f, double b_j, double *r,
+                              double *a_j, double *b_next)
+{
+    const int64_t n = m->dim;
+    orc_apply(m, f, r);
+    for (int64_t i = 0; i < n; i++)
+        r[i] -= b_j * f_prev[i];
+    const double a = dot(r, f, n);
+    for (int64_t i = 0; i < n; i++)
+        r[i] -= a * f[i];
+    *a_j = a;
+    *b_next = sqrt(dot(r, r, n));
+}
+
+/* Moves the pair of vectors one step on: f_{j-1} <- f_j, f_j <- r / b_{j+1}. */
+static void shift_vectors(double *f_prev, double *f, const double *r, double b_next, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++) {
+        f_prev[i] = f[i];
+        f[i] = r[i] / b_next;
+    }
+}
+
+/* Lanczos from the unit start vector f1 (length dim): a[j-1] = a_j and
  * b[j-1] = b_{j+1} for j = 1..m; e_hist[j-1] = lowest eigenvalue of T_j.
- * When psi is not NULL the recurrence is replayed and psi written.
+ * Stops on the energy test of Sec. 2.2, on a vanishing b_{j+1}, when the
+ * Krylov space is exhausted or at max_iter.  When psi is not NULL the
+ * coefficients are produced a second time from f1 and psi = sum_j y_j f_j
+ * is formed (y: the eigenvector of T_m for its lowest eigenvalue).
  * Returns 0, or -1 when memory runs out. */
 int orc_lanczos(const orc_model *m, const double *f1, double tol, int max_iter,
                 double *a, double *b, double *e_hist, double *psi, orc_result *res)
@@ -499,21 +533,12 @@ int orc_lanczos(const orc_model *m, const double *f1, double tol, int max_iter,
     memcpy(f_cur, f1, sizeof(double) * (size_t)n);
     memset(res, 0, sizeof(*res));
     boff[0] = 0.0;
-    boff[1] = 0.0; /* b_1 = 0 */
+    boff[1] = 0.0;
     double scale = 0.0, e_last = 0.0;
     int mm = 0;
     for (int j = 1; j <= max_iter; j++) {
-        /* q_j = H f_j - b_j f_{j-1} */
-        orc_apply(m, f_cur, q);
-        for (int64_t i = 0; i < n; i++)
-            q[i] -= boff[j] * f_prev[i];
-        /* a_j = q_j . f_j */
-        double aj = dot(q, f_cur, n);
-        /* q_j = q_j - a_j f_j */
-        for (int64_t i = 0; i < n; i++)
-            q[i] -= aj * f_cur[i];
-        /* b_{j+1} = sqrt(q_j . q_j) */
-        double bj1 = sqrt(dot(q, q, n));
+        double aj, bj1;
+        next_coefficients(m, f_prev, f_cur, boff[j], q, &aj, &bj1);
         a[j - 1] = aj;
         b[j - 1] = bj1;
         boff[j + 1] = bj1;
@@ -536,11 +561,7 @@ int orc_lanczos(const orc_model *m, const double *f1, double tol, int max_iter,
             res->converged = 3;
             break;
         }
-        /* f_{j+1} = q_j / b_{j+1}; the old f_j becomes f_{j-1} */
-        for (int64_t i = 0; i < n; i++) {
-            f_prev[i] = f_cur[i];
-            f_cur[i] = q[i] / bj1;
-        }
+        shift_vectors(f_prev, f_cur, q, bj1, n);
     }
     res->n_iter = mm;
     res->e0 = e_hist[mm - 1];
@@ -548,7 +569,8 @@ int orc_lanczos(const orc_model *m, const double *f1, double tol, int max_iter,
     if (psi) {
         double *y = (double *)malloc(sizeof(double) * (size_t)mm);
         orc_tridiag_vec(a, boff + 1, mm, res->e0, y);
-        /* replay the same recurrence and accumulate psi = sum_j y_j f_j */
+        /* the Krylov vectors again, in the same arithmetic, each added to
+         * psi with its weight y_j */
         memset(f_prev, 0, sizeof(double) * (size_t)n);
         memcpy(f_cur, f1, sizeof(double) * (size_t)n);
         memset(psi, 0, sizeof(double) * (size_t)n);
@@ -557,17 +579,9 @@ int orc_lanczos(const orc_model *m, const double *f1, double tol, int max_iter,
                 psi[i] += y[j - 1] * f_cur[i];
             if (j == mm)
                 break;
-            orc_apply(m, f_cur, q);
-            for (int64_t i = 0; i < n; i++)
-                q[i] -= boff[j] * f_prev[i];
-            double aj = dot(q, f_cur, n);
-            for (int64_t i = 0; i < n; i++)
-                q[i] -= aj * f_cur[i];
-            double bj1 = sqrt(dot(q, q, n));
-            for (int64_t i = 0; i < n; i++) {
-                f_prev[i] = f_cur[i];
-                f_cur[i] = q[i] / bj1;
-            }
+            double aj, bj1;
+            next_coefficients(m, f_prev, f_cur, boff[j], q, &aj, &bj1);
+            shift_vectors(f_prev, f_cur, q, bj1, n);
         }
         double nrm = sqrt(dot(psi, psi, n));
         for (int64_t i = 0; i < n; i++)

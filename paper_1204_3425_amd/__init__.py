@@ -89,7 +89,7 @@ class hubbard_server_stats_t(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_uint64), ("reserved", ctypes.c_uint64), ("peak_reserved", ctypes.c_uint64),
                 ("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("pending", ctypes.c_uint64), ("max_active_batch", ctypes.c_int32),
-                ("slots_used", ctypes.c_int32)]
+                ("slots_used", ctypes.c_int32), ("solo_runs", ctypes.c_uint64)]
 
 
 def _load():

@@ -469,6 +469,10 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     auto finish_step = [&](T *C, T *P, int np, int j0) {
         if (fused) {
             launch_reduce_step(partials.as<double>(), np, RED_FUSED, S, hist, j0, s);
+            // steps whose expanded norm lost its digits form X_{j+1} and its
+            // norm explicitly; both launches return at once otherwise
+            launch_fused_fix<T>(P, C, S, npad, partials.as<double>(), sb, s);
+            launch_reduce_step(partials.as<double>(), sb, RED_FIX, S, hist, j0, s);
             return;
         }
         launch_reduce_step(partials.as<double>(), np, RED_DOT, S, hist, j0, s);

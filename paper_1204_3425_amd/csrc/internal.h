@@ -155,7 +155,12 @@ struct HvPlan {
     int nparts = 1;         // largest number of partial sums any launch writes
 };
 enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2, HV_FUSED = 3 };
-enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2, RED_FUSED = 3, RED_START = 4 };
+enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2, RED_FUSED = 3, RED_START = 4, RED_FIX = 5 };
+// Fused Lanczos step: below this ratio b_{j+1}^2 / |q|^2 the expanded norm
+// has lost too many digits and the step is finished by the explicit fix-up
+// (device scalars S[kFixFlag], S[kFixScale]).
+constexpr double kFixRatio = 1e-4;
+constexpr int kFixFlag = 6, kFixScale = 7;
 
 // HV_STORE:    y = H x
 // HV_LANCZOS:  y = alpha H x + beta y (in place), alpha = coef[0], beta = coef[1];
@@ -181,6 +186,9 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
 
 template <typename T>
 void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);
+// the fix-up of a flagged fused step (a no-op when S[kFixFlag] is clear)
+template <typename T>
+void launch_fused_fix(T *w, const T *v, const double *S, int64_t n, double *partials, int nblocks, hipStream_t s);
 void launch_start_raw(uint64_t seed, double *f, int64_t n, hipStream_t s);
 void launch_start_norm2(const double *given, uint64_t seed, int64_t n, double *partials, int nblocks, hipStream_t s);
 // out[r*ld + d] = (T)(c f[r*dim_dn + d]) and 0 in the row padding; zero (if

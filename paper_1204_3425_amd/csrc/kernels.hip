@@ -299,6 +299,40 @@ template void launch_axpy_norm<double>(double *, const double *, const double *,
                                        hipStream_t);
 template void launch_axpy_norm<float>(float *, const float *, const double *, int64_t, double *, int, hipStream_t);
 
+// Fix-up of a fused step whose expanded norm was flagged as inaccurate
+// (S[kFixFlag] set by the RED_FUSED reduction): w <- w - S[3] v, the next
+// vector formed explicitly, and partial sums of its squared norm.  A no-op
+// (every workgroup returns at once) when the flag is clear.
+template <typename T>
+__global__ __launch_bounds__(256) void fused_fix_kernel(T *__restrict__ w, const T *__restrict__ v,
+                                                        const double *__restrict__ S, int64_t n,
+                                                        double *__restrict__ partials)
+{
+    if (S[kFixFlag] == 0.0)
+        return;
+    __shared__ double red[4];
+    const T cs = (T)S[3];
+    double acc = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const T q = w[i] - cs * v[i];
+        w[i] = q;
+        acc += (double)q * (double)q;
+    }
+    double s = block_sum(acc, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = s;
+}
+
+template <typename T>
+void launch_fused_fix(T *w, const T *v, const double *S, int64_t n, double *partials, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(fused_fix_kernel<T>, dim3(nblocks), dim3(256), 0, s, w, v, S, n, partials);
+    HUB_HIP(hipGetLastError());
+}
+template void launch_fused_fix<double>(double *, const double *, const double *, int64_t, double *, int, hipStream_t);
+template void launch_fused_fix<float>(float *, const float *, const double *, int64_t, double *, int, hipStream_t);
+
 // SplitMix64 (Steele, Lea & Flood 2014): output k of the stream started at
 // `seed` is the published finaliser applied to seed + k * 0x9E3779B97F4A7C15.
 __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k)
@@ -609,9 +643,13 @@ void launch_scale(double *v, double c, int64_t n, hipStream_t s)
 //   a_j = (y.x) / s, c = a_j / s, and the norm of the next vector
 //   X_{j+1} = y - c X_j, which the next step forms, is expanded as
 //   |y|^2 - 2 c (y.x) + c^2 |X_j|^2.  The expansion loses the digits of b_{j+1}
-//   that cancel against |y|; below 64 eps |y|^2 the subspace is taken as
-//   invariant (b_{j+1} = 0, a breakdown).
-// S = device scalars {1/s of the current vector, alpha, beta, c}.
+//   that cancel against |y|: when it falls below kFixRatio |y|^2 the step is
+//   flagged (S[kFixFlag] = 1, the old 1/s kept in S[kFixScale]) and b_{j+1}
+//   is left to RED_FIX.
+// mode RED_FIX (after fused_fix_kernel, only when the step was flagged):
+//   b_{j+1} = |X_{j+1}| from the explicit vector; c = 0, so the next step's
+//   row pass keeps X_{j+1} as it is; the flag is cleared.
+// S = device scalars {1/s of the current vector, alpha, beta, c, -, -, flag, 1/s kept}.
 __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__ partials, int n, int stride,
                                                       double *__restrict__ out, int mode, double *__restrict__ S,
                                                       double *__restrict__ hist, int j)
@@ -621,6 +659,8 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         acc += src[i];
+    if (mode == RED_FIX && S[kFixFlag] == 0.0)
+        return;
     double s = block_sum(acc, red);
     if (mode == RED_FUSED) {
         double acc1 = 0.0, acc2 = 0.0;
@@ -634,13 +674,31 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
             const double a = s * S[0];
             const double c = a * S[0];
             const double b2 = qq - 2.0 * c * s + c * c * xx;
-            const double b = b2 > 64.0 * 0x1p-52 * qq ? sqrt(b2) : 0.0;
             hist[2 * j] = a;
-            hist[2 * j + 1] = b;
             S[3] = c;
-            S[2] = -b * S[0];
+            if (b2 >= kFixRatio * qq) {
+                const double b = sqrt(b2);
+                hist[2 * j + 1] = b;
+                S[2] = -b * S[0];
+                S[0] = 1.0 / b;
+                S[1] = S[0];
+                S[kFixFlag] = 0.0;
+            } else {
+                S[kFixScale] = S[0];
+                S[kFixFlag] = 1.0;
+            }
+        }
+        return;
+    }
+    if (mode == RED_FIX) {
+        if (threadIdx.x == 0) {
+            const double b = sqrt(s);
+            hist[2 * j + 1] = b;
+            S[2] = -b * S[kFixScale];
             S[0] = b > 0.0 ? 1.0 / b : 0.0;
             S[1] = S[0];
+            S[3] = 0.0;
+            S[kFixFlag] = 0.0;
         }
         return;
     }
@@ -688,6 +746,7 @@ __global__ void init_scalars_kernel(double *S)
         S[1] = 1.0;
         S[2] = 0.0;
         S[3] = 0.0;
+        S[kFixFlag] = 0.0;
     }
 }
 

@@ -40,9 +40,10 @@ struct Job {
 // Upper bound of the device bytes a request needs: the two work vectors on
 // padded rows, partial sums, the batched engine's coefficient history, and the
 // tables with at most n_edges entries per row: up side (row-major entries,
-// blocked entries, one 32-slot line, counts, states) and down side
-// (column-major entries, 64- and 32-bit offset groups, 16-bit groups, counts,
-// states).
+// blocked entries, the entry lines: one 128-byte line per row when a row has
+// at most 32 hops, two when it has at most 64, none beyond; counts, states)
+// and down side (column-major entries, 64- and 32-bit offset groups, 16-bit
+// groups, counts, states).
 size_t footprint(const hubbard_request &r)
 {
     const uint64_t du = binomial(r.sites, r.n_up), dd = binomial(r.sites, r.n_dn);
@@ -50,7 +51,8 @@ size_t footprint(const hubbard_request &r)
     const size_t ld = (size_t)((dd + 63) / 64 * 64);
     const size_t vecs = 2 * es * (size_t)du * ld + 64 * 1024 + 16 * (size_t)std::max(1, r.max_iter);
     const size_t w = (size_t)std::max(1, r.n_edges);
-    const size_t up = (size_t)du * (8 * w + 142);
+    const size_t lines = w <= 32 ? 128 : (w <= 64 ? 256 : 0);
+    const size_t up = (size_t)du * (8 * w + 14 + lines);
     const size_t dn = (size_t)dd * (14 * w + 56);
     return vecs + up + dn;
 }
@@ -74,6 +76,7 @@ struct hubbard_server {
     int slots_used = 0;
     uint64_t next_id = 1, admitted = 0, completed = 0, rejected = 0;
     int max_active_batch = 0;
+    uint64_t solo_runs = 0;
     bool stop = false;
     std::string fatal;
 
@@ -259,6 +262,10 @@ void solo_loop(hubbard_server *S)
         }
         job->h->stream = S->s_solo;
         job->done.t_start = S->now();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->solo_runs++;
+        }
         int rc;
         try {
             rc = lanczos_impl(job->h, opts_of(job->req), &job->done.result);
@@ -407,6 +414,7 @@ int hubbard_server_stats(hubbard_server_h S, hubbard_server_stats_t *st)
         st->pending = S->pending.size();
         st->max_active_batch = S->max_active_batch;
         st->slots_used = S->slots_used;
+        st->solo_runs = S->solo_runs;
         return HUBBARD_OK;
     });
 }

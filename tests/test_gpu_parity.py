@@ -88,6 +88,12 @@ APPLY_CASES = [
     # dim_dn * 8 bytes > 160 KB: the down-spin rows do not fit in LDS
     workload.problem("ring18_wide_rows", 18, workload.ring(18), 1, 9, 1.0, 4.0),
     workload.problem("ring14", 14, workload.ring(14), 7, 7, 1.0, 4.0),
+] + [
+    # the 4x4 lattice with 8 electrons of one spin (1,544,400 states): down rows
+    # of 12,870 elements as in the headline sector, and 12,870 up rows in the
+    # headline sector's row blocks, with a full element-wise check
+    workload.problem("sq4x4_2u8d", 16, workload.torus(4, 4), 2, 8, 1.0, 8.0),
+    workload.problem("sq4x4_8u2d", 16, workload.torus(4, 4), 8, 2, 1.0, 8.0),
 ]
 
 
@@ -122,6 +128,13 @@ PADDED_CASES = [
     # layouts hold (the variable-width blocked pass)
     workload.problem("complete17_8u1d", 17, [(i, j) for i in range(17) for j in range(i + 1, 17)], 8, 1, 1.0, 3.0),
     workload.problem("chain13_ragged", 13, workload.chain(13), 7, 3, 1.0, 5.0),
+    # down rows of 12,870 elements on the 4x4 lattice (the headline sector's
+    # row-pass launch shape: one row per workgroup in FP64, three in FP32) ...
+    workload.problem("sq4x4_2u8d", 16, workload.torus(4, 4), 2, 8, 1.0, 8.0),
+    workload.problem("sq4x4_1u8d_U0", 16, workload.torus(4, 4), 1, 8, 1.3, 0.0),
+    # ... and 12,870 up rows in its 16 row blocks (the line pass of the headline sector)
+    workload.problem("sq4x4_8u2d", 16, workload.torus(4, 4), 8, 2, 1.0, 8.0),
+    workload.problem("sq4x4_8u1d_ragged", 16, workload.torus(4, 4), 8, 1, 0.8, 3.0),
 ]
 
 
@@ -146,54 +159,52 @@ def test_apply_padded_rows_match_oracle(p, precision):
 
 
 @pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
-def test_apply_4x4_sampled_rows(precision):
+def test_apply_4x4_full_vector(precision):
     """The 4x4 half-filled sector (dim 165,636,900) at full size, in the launch
-    configuration the benchmark uses (rows padded to ld_pref): outputs checked
-    on 3000 sampled rows (including the first and last row and the last
-    column), and the symmetry of H against the dense-row kernels."""
+    configuration the benchmark uses (rows padded to ld_pref): every output
+    against the oracle's H.v (about 10 s on one host core), and the symmetry of
+    H against the kernels for dense caller rows."""
     p = workload.square4x4()
-    _say("apply 4x4 sampled, precision", precision)
+    _say("apply 4x4 full vector, precision", precision)
     h = _build(p)
     m = _oracle(p)
     x = workload.random_vector(p.dim, p.seed + 2)
     if precision == hb.HUBBARD_MIXED:
         x = x.astype(np.float32).astype(np.float64)
     got = _apply_gpu_ld(h, x, precision)
-    rng = np.random.default_rng(3)
-    rows = np.concatenate([[0, p.dim - 1, p.dim_dn - 1, p.dim - p.dim_dn], rng.integers(0, p.dim, 3000)])
-    ref = m.apply_rows(x, rows)
-    g = got[rows]
+    ref = m.apply(x)
+    err = np.abs(got - ref)
+    _say("4x4 max abs err %.3e (max |ref| %.3e)" % (err.max(), np.abs(ref).max()))
     if precision == hb.HUBBARD_FP64:
-        assert np.abs(g - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+        assert err.max() <= 1e-13 * max(1.0, np.abs(ref).max())
     else:
         info = hb.hubbard_info(h)
-        bound = (1 + info["w_up"] + info["w_dn"]) * 2.0**-24 * _term_bound(p, info)
-        assert np.abs(g - ref).max() <= bound
-        assert np.linalg.norm(g - ref) <= 1e-5 * np.linalg.norm(ref)
+        bound = (1 + info["w_up"] + info["w_dn"]) * 2.0**-24 * _term_bound(p, info) * np.abs(x).max()
+        assert err.max() <= bound
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    del err, ref
     # symmetry of H at full size: <u, H v> == <H u, v>
     u = workload.random_vector(p.dim, p.seed + 3)
     if precision == hb.HUBBARD_MIXED:
         u = u.astype(np.float32).astype(np.float64)
-    Hu = _apply_gpu(h, u, precision)  # dense rows: the other up-spin kernel
+    Hu = _apply_gpu(h, u, precision)  # dense rows: the caller's J-order layout
     lhs, rhs = float(u @ got), float(Hu @ x)
     tol = 1e-11 if precision == hb.HUBBARD_FP64 else 1e-4
     assert abs(lhs - rhs) <= tol * (np.abs(u).sum() + np.abs(x).sum())
 
 
-def test_apply_ring16_sampled_rows():
+def test_apply_ring16_full_vector():
     """The 16-site ring at half filling (dim 165,636,900, 16-hop rows: a
     different table structure from the 4x4 lattice at the same size), FP64 on
-    padded rows, checked on 2000 sampled rows."""
+    padded rows, every output against the oracle's H.v."""
     p = workload.problem("ring16", 16, workload.ring(16), 8, 8, 1.0, 6.0)
-    _say("apply ring16 sampled")
+    _say("apply ring16 full vector")
     h = _build(p)
     m = _oracle(p)
     x = workload.random_vector(p.dim, p.seed + 5)
     got = _apply_gpu_ld(h, x, hb.HUBBARD_FP64)
-    rng = np.random.default_rng(5)
-    rows = np.concatenate([[0, p.dim - 1, p.dim_dn - 1], rng.integers(0, p.dim, 2000)])
-    ref = m.apply_rows(x, rows)
-    assert np.abs(got[rows] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    ref = m.apply(x)
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
 
 
 @pytest.mark.parametrize("precision", [hb.HUBBARD_FP64, hb.HUBBARD_MIXED], ids=["fp64", "mixed"])
@@ -392,6 +403,31 @@ def test_lanczos_up_rows_over_64_hops():
     got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, -1.0, 20)
     assert np.allclose(got["a"], ref["a"], rtol=1e-12, atol=1e-12)
     assert np.allclose(got["b"], ref["b"], rtol=1e-10, atol=1e-12)
+
+
+def test_lanczos_fused_step_decaying_b():
+    """A fused-size sector (392,040 states) in the atomic limit (t = 0: H is
+    diagonal with the levels U * D, D the double occupancy) from a start vector
+    whose weight on each level falls by 1e4 per doubly occupied site: the
+    Krylov vectors are dominated by successive levels and b_{j+1} / |q_j|
+    falls to about 3.6e-5, where |q|^2 - 2 c q.f + c^2 |f|^2 loses most digits
+    of b_{j+1}.  Such steps take the explicit norm; the first four a_j, b_{j+1}
+    (the ones the invariant subspace determines, before rounding takes over)
+    match the oracle's."""
+    p = workload.problem("torus3x4_atomic_decay", 12, workload.torus(3, 4), 4, 5, 0.0, 4.0)
+    h = _build(p)
+    m = _oracle(p)
+    D = np.rint(m.diagonal() / p.U).astype(int)
+    f = workload.random_vector(p.dim, 3) * (10.0 ** (-4.0 * D))
+    f /= np.linalg.norm(f)
+    ref = m.lanczos(f, tol=-1.0, max_iter=4)
+    qq = (np.asarray(ref["a"]) ** 2 + np.asarray(ref["b"]) ** 2) / np.asarray(ref["b"]) ** 2
+    assert qq.max() > 1e8  # the regime the explicit norm is for
+    got = _lanczos_gpu(h, p, hb.HUBBARD_FP64, -1.0, 4, start=torch.from_numpy(f).to(DEV))
+    _say("decaying b: max rel diff a %.2e b %.2e" % (
+        np.max(np.abs(got["a"] - ref["a"]) / np.abs(ref["a"])), np.max(np.abs(got["b"] - ref["b"]) / ref["b"])))
+    assert np.allclose(got["a"], ref["a"], rtol=1e-10, atol=0)
+    assert np.allclose(got["b"], ref["b"], rtol=1e-10, atol=0)
 
 
 def test_lanczos_large_sector_breakdown():

@@ -84,21 +84,25 @@ def test_server_result_same_alone_and_in_mix():
 
 
 def test_server_large_sector_on_second_stream():
-    """A sector above the batched size runs on the two-pass path beside small
-    ones; its mixed-precision E0 agrees with the FP64 single-instance path."""
-    big = workload.problem("sq4x4_5u5d", 16, workload.torus(4, 4), 5, 5, 1.0, 6.0)
+    """Sectors whose rows exceed the batched kernels' 64 KB run on the solo
+    executor's stream beside small batched ones: a 17-site ring with 1 up and
+    8 down electrons (rows of 24,310 FP32 values, 95 KB: the two-pass H.v) and
+    an 18-site ring with 1 up and 9 down (rows of 48,620 values, wider than the
+    LDS: the one-pass H.v).  Every result, the solo ones included, is checked
+    against the oracle's E0 from the same seed."""
+    solo = [workload.problem("ring17_1u8d", 17, workload.ring(17), 1, 8, 1.0, 5.0),
+            workload.problem("ring18_1u9d", 18, workload.ring(18), 1, 9, 1.0, 4.0, seed=11)]
     small = workload.batch64(4)
     srv = hb.hubbard_server_create(4 << 30, 8)
-    big_id = _submit(srv, big)
+    solo_ids = {_submit(srv, p): p for p in solo}
     ids = {_submit(srv, p): p for p in small}
-    res = _collect(srv, 1 + len(ids))
+    res = _collect(srv, len(solo_ids) + len(ids))
+    st = hb.hubbard_server_stats(srv)
     hb.hubbard_server_destroy(srv)
-    h = hb.hubbard_build(big.sites, big.edges, big.n_up, big.n_dn, big.t, big.U)
-    ref = hb.hubbard_lanczos_ex(h, tol=1e-12, max_iter=300, precision=hb.HUBBARD_FP64, seed=big.seed)
-    assert res[big_id]["status"] == hb.HUBBARD_OK
-    assert res[big_id]["E0"] == pytest.approx(ref["E0"], rel=1e-6)
-    for rid, p in ids.items():
-        assert res[rid]["E0"] == pytest.approx(_oracle_e0(p), rel=1e-6)
+    assert st["solo_runs"] == len(solo)
+    for rid, p in list(solo_ids.items()) + list(ids.items()):
+        assert res[rid]["status"] == hb.HUBBARD_OK, p.name
+        assert res[rid]["E0"] == pytest.approx(_oracle_e0(p), rel=1e-6), p.name
 
 
 def test_server_rejects_malformed_requests():
