@@ -411,9 +411,12 @@ def test_lanczos_fused_step_decaying_b():
     whose weight on each level falls by 1e4 per doubly occupied site: the
     Krylov vectors are dominated by successive levels and b_{j+1} / |q_j|
     falls to about 3.6e-5, where |q|^2 - 2 c q.f + c^2 |f|^2 loses most digits
-    of b_{j+1}.  Such steps take the explicit norm; the first four a_j, b_{j+1}
-    (the ones the invariant subspace determines, before rounding takes over)
-    match the oracle's."""
+    of b_{j+1} (about 1e-8 of it here).  Such steps take the explicit norm.
+    Compared: a_1..a_4 and b_2..b_4.  b_5 is left out: it measures the weight
+    of the highest level (D = 4) in f_4, and the start vector gives that level
+    1e-16 of the amplitude of the lowest one: the size of the rounding errors
+    every step of the recurrence adds to all levels, so b_5 is set by rounding
+    on both sides (they differ by about 1e-5 of it)."""
     p = workload.problem("torus3x4_atomic_decay", 12, workload.torus(3, 4), 4, 5, 0.0, 4.0)
     h = _build(p)
     m = _oracle(p)
@@ -427,7 +430,7 @@ def test_lanczos_fused_step_decaying_b():
     _say("decaying b: max rel diff a %.2e b %.2e" % (
         np.max(np.abs(got["a"] - ref["a"]) / np.abs(ref["a"])), np.max(np.abs(got["b"] - ref["b"]) / ref["b"])))
     assert np.allclose(got["a"], ref["a"], rtol=1e-10, atol=0)
-    assert np.allclose(got["b"], ref["b"], rtol=1e-10, atol=0)
+    assert np.allclose(got["b"][:3], ref["b"][:3], rtol=1e-10, atol=0)
 
 
 def test_lanczos_large_sector_breakdown():
