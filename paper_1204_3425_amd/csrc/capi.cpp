@@ -97,7 +97,7 @@ static void free_device(hubbard *h)
 {
     DeviceTables &d = h->dev;
     void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
-                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.up_blk, d.up_nint, d.up_next,
+                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.dn_idx16, d.dn_sgn64, d.up_blk, d.up_nint, d.up_next,
                     d.up_bstart, d.up_line, d.up_cnt, d.tcls};
     for (void *p : ptrs)
         if (p)
@@ -273,7 +273,8 @@ static void upload_tables(hubbard *h)
         // entry k of column d at ((k/8) * dim_dn + d) * 8 + k%8; padding = the zero slot's index
         const int ng8 = (h->dn.width + 7) / 8;
         std::vector<uint16_t> g((size_t)std::max(ng8, 1) * (size_t)ddn * 8, (uint16_t)ddn);
-        std::vector<uint8_t> nq8((size_t)((ddn + 63) / 64), 0);
+        // padded to whole 32-bit words (the FP64 row pass reads it by words)
+        std::vector<uint8_t> nq8((size_t)((ddn + 255) / 256) * 4, 0);
         for (int64_t r = 0; r < ddn; r++) {
             const int nnz = h->dn.row_nnz[(size_t)r];
             for (int k = 0; k < nnz; k++) {
@@ -286,6 +287,26 @@ static void upload_tables(hubbard *h)
         }
         d.dn_groups16 = upload<uint16_t>(g.data(), g.size() * 2, total);
         d.dn_nq8 = upload<uint8_t>(nq8.data(), nq8.size(), total);
+        if (ddn <= kRow64Max) {
+            // the FP64 row pass: indices alone, signs as one bit per lane of
+            // a 64-column group and entry slot
+            const int64_t ngrp = (ddn + 63) / 64;
+            std::vector<uint16_t> gi((size_t)std::max(ng8, 1) * (size_t)ddn * 8, (uint16_t)ddn);
+            std::vector<uint64_t> sg((size_t)ngrp * (size_t)std::max(ng8, 1) * 8, 0ull);
+            for (int64_t r = 0; r < ddn; r++) {
+                const int nnz = h->dn.row_nnz[(size_t)r];
+                for (int k = 0; k < nnz; k++) {
+                    size_t src = (size_t)k * (size_t)ddn + (size_t)r;
+                    gi[((size_t)(k / 8) * (size_t)ddn + (size_t)r) * 8 + (size_t)(k % 8)] =
+                        (uint16_t)h->dn.col[src];
+                    if (h->dn.sgn[src] < 0)
+                        sg[((size_t)(r / 64) * (size_t)std::max(ng8, 1) + (size_t)(k / 8)) * 8 + (size_t)(k % 8)] |=
+                            1ull << (r % 64);
+                }
+            }
+            d.dn_idx16 = upload<uint16_t>(gi.data(), gi.size() * 2, total);
+            d.dn_sgn64 = upload<uint64_t>(sg.data(), sg.size() * 8, total);
+        }
     }
     upload_blocked_up(h, total);
     d.bytes = total;
@@ -312,6 +333,8 @@ static HvArgs hv_args(const hubbard *h)
     a.dn_ngroups = h->dev.dn_ngroups;
     a.dn_groups16 = reinterpret_cast<const uint4 *>(h->dev.dn_groups16);
     a.dn_nq8 = h->dev.dn_nq8;
+    a.dn_idx16 = reinterpret_cast<const uint4 *>(h->dev.dn_idx16);
+    a.dn_sgn64 = h->dev.dn_sgn64;
     a.up_blk = h->dev.up_blk;
     a.up_nint = h->dev.up_nint;
     a.up_next = h->dev.up_next;

@@ -6,7 +6,8 @@
 // The two hopping terms want different data movement, so each gets a pass of
 // its own:
 //
-// Row pass (I (x) H_dn and the interaction).  A workgroup stages whole rows of
+// Row pass (I (x) H_dn and the interaction).  hv_rows64_kernel for FP64 rows that
+// fill the LDS (one amplitude), hv_rows_kernel otherwise.  A workgroup stages whole rows of
 // X in LDS (RPB rows at once, each followed by a zero slot; every thread loads
 // its chunk before writing any of it) and every lane produces the outputs of
 // its columns d by gathering X[r, e_k(d)] from LDS.  The down table is stored
@@ -39,6 +40,8 @@
 // Partial sums are one FP64 value per up-spin-pass workgroup, summed later in
 // a fixed order.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "internal.h"
 
@@ -236,6 +239,216 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                             *yp = hx - a_s * xv;
                     }
                 }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// FP64 row pass (one amplitude; rows of at most 13,312 elements).
+//
+// The same product as hv_rows_kernel with one row per workgroup (an FP64 row
+// of the 4x4 lattice fills the LDS), with fewer instructions per entry: the
+// 16-bit element index becomes the byte address by one shift that reads the
+// half word in place (SDWA), and the entry's sign comes from a 64-bit word
+// shared by the wave (bit l for lane l, one word per entry slot of 64
+// columns, loaded with scalar loads), which picks the high half of +1 or -1
+// for the FMA that adds the gathered value: three instructions per entry
+// instead of about six.  The row sits in a statically sized LDS array, so an
+// address needs no base.  A column's entry groups are loaded one column
+// ahead, and the next row is loaded into registers (16-byte loads) while the
+// current one is gathered and written to LDS after the barrier that ends it.
+constexpr int kRowThreads = 1024;
+
+struct Row64Args {
+    const uint4 *__restrict__ idx;      // [g][d] -> eight 16-bit element indices
+    const uint64_t *__restrict__ sgn;   // [(d / 64) * ng + g][8]
+    const uint8_t *__restrict__ nq;     // groups of eight per 64 columns
+    const uint32_t *__restrict__ states_up;
+    const uint32_t *__restrict__ states_dn;
+    int64_t dim_up;
+    int dim_dn, ng;
+    double t, U;
+};
+
+__device__ inline uint32_t lds_off_lo(uint32_t e)
+{
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(r)
+        : "v"(e));
+    return r;
+}
+__device__ inline uint32_t lds_off_hi(uint32_t e)
+{
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+        : "=v"(r)
+        : "v"(e));
+    return r;
+}
+// high half of +1.0 or -1.0, chosen by this lane's bit of the wave-uniform mask
+__device__ inline int sign_hi(uint64_t mask, int pos_hi, int neg_hi)
+{
+    int r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(pos_hi), "v"(neg_hi), "s"(mask));
+    return r;
+}
+
+template <int MODE, bool VEC, int CH, int NG>
+__global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, const double *__restrict__ x, int64_t ldx,
+                                                                double *__restrict__ y, int64_t ldy, double alpha,
+                                                                double beta, const double *__restrict__ coef)
+{
+    __shared__ __align__(16) double xs[kRow64Max + 2];
+    double cshift = 0.0;
+    if (MODE == HV_LANCZOS) {
+        alpha = coef[0];
+        beta = coef[1];
+    } else if (MODE == HV_FUSED) {
+        alpha = coef[1];
+        beta = coef[2];
+        cshift = coef[3];
+    }
+    const int ddn = p.dim_dn, tid = (int)threadIdx.x;
+    // staging units: 16-byte pairs (rows 16-byte aligned) or single elements
+    typedef typename std::conditional<VEC, double2, double>::type SU;
+    const int nu = VEC ? ddn >> 1 : ddn;
+    const bool tail = VEC && (ddn & 1) && tid == kRowThreads - 1;  // the odd last element of a VEC row
+    SU v[CH], w[CH];
+    double vt = 0.0, wt = 0.0;
+    auto load_row = [&](int64_t r) {
+        const SU *src = reinterpret_cast<const SU *>(x + r * ldx);
+        const SU *ysrc = reinterpret_cast<const SU *>(y + r * ldy);
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int i = u * kRowThreads + tid;
+            if (i < nu) {
+                v[u] = src[i];
+                if (MODE == HV_FUSED)
+                    w[u] = ysrc[i];
+            }
+        }
+        if (tail) {
+            vt = x[r * ldx + ddn - 1];
+            if (MODE == HV_FUSED)
+                wt = y[r * ldy + ddn - 1];
+        }
+    };
+    auto store_row = [&](int64_t r) {
+        SU *xs2 = reinterpret_cast<SU *>(xs);
+        SU *xw = reinterpret_cast<SU *>(const_cast<double *>(x) + r * ldx);
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int i = u * kRowThreads + tid;
+            if (i < nu) {
+                SU val = v[u];
+                if (MODE == HV_FUSED) {
+                    // the q - a_j f_j update of the previous step, formed here and kept
+                    val = val - cshift * w[u];
+                    xw[i] = val;
+                }
+                xs2[i] = val;
+            }
+        }
+        if (tail) {
+            double val = vt;
+            if (MODE == HV_FUSED) {
+                val = val - cshift * wt;
+                const_cast<double *>(x)[r * ldx + ddn - 1] = val;
+            }
+            xs[ddn - 1] = val;
+        }
+        if (tid == 0)
+            xs[ddn] = 0.0;  // the zero slot that padding entries point at
+    };
+
+    const double mt = -p.t, U = p.U;
+    const int pos_hi = 0x3FF00000, neg_hi = (int)0xBFF00000;
+    const uint32_t *__restrict__ nq32 = reinterpret_cast<const uint32_t *>(p.nq);
+    // groups of eight entries of the wave's 64 columns (0 past the row; wave-uniform)
+    auto group_count = [&](int grp) -> int {
+        return grp * 64 < ddn ? (int)((nq32[grp >> 2] >> ((grp & 3) * 8)) & 0xffu) : 0;
+    };
+    // a column's entry groups (all of them, so one memory round trip per column)
+    auto load_groups = [&](int d, int nq, uint4 (&e)[NG], uint32_t &sd) {
+        const int dd = d < ddn ? d : ddn - 1;
+#pragma unroll
+        for (int g = 0; g < NG; g++)
+            if (g < nq)
+                e[g] = p.idx[(size_t)g * (size_t)ddn + (size_t)dd];
+        sd = p.states_dn[dd];
+    };
+    int64_t r = blockIdx.x;
+    if (r < p.dim_up)
+        load_row(r);
+    for (; r < p.dim_up; r += gridDim.x) {
+        store_row(r);
+        __syncthreads();
+        // the next row's loads stay in flight while this one is gathered
+        if (r + gridDim.x < p.dim_up)
+            load_row(r + gridDim.x);
+        const uint32_t su = p.states_up[r];
+        int grp = __builtin_amdgcn_readfirstlane(tid >> 6);
+        int nq = group_count(grp);
+        uint4 e[NG];
+        uint32_t sd = 0;
+        load_groups(tid, nq, e, sd);
+        for (int d0 = 0; d0 < ddn; d0 += kRowThreads) {
+            const int d = d0 + tid;
+            // the next column's entries load while this one is gathered
+            const int grpn = grp + kRowThreads / 64;
+            const int nqn = group_count(grpn);
+            uint4 en[NG];
+            uint32_t sdn = 0;
+            constexpr bool ahead = MODE != HV_FUSED;  // the fused mode has no registers to spare
+            if (ahead && d0 + kRowThreads < ddn)
+                load_groups(d + kRowThreads, nqn, en, sdn);
+            if (nq > 0) {
+                const uint64_t *__restrict__ sp = p.sgn + (size_t)grp * (size_t)p.ng * 8;
+                double h0 = 0.0, h1 = 0.0;
+#pragma unroll
+                for (int g = 0; g < NG; g++) {
+                    if (g < nq) {
+                        uint64_t m[8];
+#pragma unroll
+                        for (int u = 0; u < 8; u++)
+                            m[u] = sp[g * 8 + u];
+                        const uint32_t ev[4] = {e[g].x, e[g].y, e[g].z, e[g].w};
+                        double xv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; u++) {
+                            const uint32_t a = (u & 1) ? lds_off_hi(ev[u >> 1]) : lds_off_lo(ev[u >> 1]);
+                            xv[u] = *reinterpret_cast<const double *>(reinterpret_cast<const unsigned char *>(xs) + a);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; u += 2) {
+                            h0 = fma(__hiloint2double(sign_hi(m[u], pos_hi, neg_hi), 0), xv[u], h0);
+                            h1 = fma(__hiloint2double(sign_hi(m[u + 1], pos_hi, neg_hi), 0), xv[u + 1], h1);
+                        }
+                    }
+                }
+                if (d < ddn) {
+                    const double xd = xs[d];
+                    const double hx = fma(mt, h0 + h1, U * (double)__popc(su & sd) * xd);
+                    double *yp = y + r * ldy + d;
+                    if (MODE == HV_STORE)
+                        *yp = hx;
+                    else if (MODE == HV_LANCZOS || MODE == HV_FUSED)
+                        *yp = alpha * hx + beta * *yp;
+                    else
+                        *yp = hx - alpha * xd;
+                }
+            }
+            grp = grpn;
+            nq = nqn;
+            if (ahead) {
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    e[g] = en[g];
+                sd = sdn;
+            } else if (d0 + kRowThreads < ddn) {
+                load_groups(d + kRowThreads, nqn, e, sd);
             }
         }
         __syncthreads();
@@ -906,6 +1119,60 @@ static void launch_rows_rpb(const RowArgs &ra, bool g16, bool gt, const HvPlan &
     }
 }
 
+// The FP64 row pass takes handles of one amplitude whose rows need the whole
+// LDS (one row per workgroup) and fit kRow64Max elements.
+static bool row64_ok(const HvArgs &a, const HvPlan &pl)
+{
+    // rows of up to 13 elements per thread are staged through registers
+    return a.tcls == nullptr && a.dn_idx16 != nullptr && a.dn_sgn64 != nullptr && pl.rows_rpb == 1 &&
+           a.w_dn <= 32 && a.dim_dn <= 13 * kRowThreads;
+}
+
+// The FP64 row pass of hv_rows64_kernel: CH staging units per thread (16-byte
+// pairs when x and y rows start on 16 bytes, else single elements).
+template <int MODE>
+static void launch_rows64_mode(const Row64Args &ra, const HvPlan &pl, const double *x, int64_t ldx, double *y,
+                               int64_t ldy, double alpha, const double *coef, hipStream_t s)
+{
+    const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0) && ldx % 2 == 0 && ldy % 2 == 0;
+    const int64_t units = vec ? ra.dim_dn / 2 : ra.dim_dn;
+    const int need = (int)((units + kRowThreads - 1) / kRowThreads);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(pl.rows_grid), dim3(kRowThreads), 0, s, ra, x, ldx, y, ldy, alpha, 0.0, coef);
+        HUB_HIP(hipGetLastError());
+    };
+    if (need > (vec ? 7 : 13))
+        fail(HUBBARD_EDEVICE, "row too long for the FP64 row pass");
+    if (vec)
+        go(hv_rows64_kernel<MODE, true, 7, 4>);
+    else
+        go(hv_rows64_kernel<MODE, false, 13, 4>);
+}
+
+static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, int64_t ldx, double *y, int64_t ldy,
+                          int mode, double alpha, const double *coef, hipStream_t s)
+{
+    Row64Args ra;
+    ra.idx = a.dn_idx16;
+    ra.sgn = a.dn_sgn64;
+    ra.nq = a.dn_nq8;
+    ra.states_up = a.states_up;
+    ra.states_dn = a.states_dn;
+    ra.dim_up = a.dim_up;
+    ra.dim_dn = (int)a.dim_dn;
+    ra.ng = (a.w_dn + 7) / 8 > 0 ? (a.w_dn + 7) / 8 : 1;
+    ra.t = a.t;
+    ra.U = a.U;
+    if (mode == HV_STORE)
+        launch_rows64_mode<HV_STORE>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+    else if (mode == HV_LANCZOS)
+        launch_rows64_mode<HV_LANCZOS>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+    else if (mode == HV_FUSED)
+        launch_rows64_mode<HV_FUSED>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+    else
+        launch_rows64_mode<HV_RESIDUAL>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+}
+
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s)
@@ -934,7 +1201,10 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     ra.U = a.U;
     T *yr = mode == HV_RESIDUAL ? scratch : y;
     const int64_t ldyr = mode == HV_RESIDUAL ? lds_ : ldy;
-    if (pl.rows_rpb == 3)
+    if (sizeof(T) == 8 && row64_ok(a, pl))
+        launch_rows64(a, pl, reinterpret_cast<const double *>(x), ldx, reinterpret_cast<double *>(yr), ldyr, mode,
+                      alpha, coef, s);
+    else if (pl.rows_rpb == 3)
         launch_rows_rpb<T, 3>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else if (pl.rows_rpb == 2)
         launch_rows_rpb<T, 2>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);

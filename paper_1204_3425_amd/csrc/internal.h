@@ -48,6 +48,8 @@ constexpr int kMaxAmpClasses = 127;
 // per-bond handles with at most this many classes also get the two-pass tables
 // (two class bits in the row-pass groups and the up-spin entries)
 constexpr int kTwoPassClasses = 4;
+// longest row the FP64 row pass stages in LDS (plus one zero slot: 160 KB)
+constexpr int kRow64Max = 20000;
 
 struct DeviceTables {
     uint32_t *states_up = nullptr, *states_dn = nullptr;
@@ -64,6 +66,12 @@ struct DeviceTables {
     // groups of eight 16-bit entries (element index | sign<<15)
     uint16_t *dn_groups16 = nullptr;
     uint8_t *dn_nq8 = nullptr;     // groups of eight needed by the 64 columns of a wave
+    // FP64 row pass (one amplitude, rows of at most kRow64Max elements): the
+    // same groups of eight holding the element index alone (padding: the zero
+    // slot at index dim_dn), and the signs apart, one 64-bit word per group
+    // of 64 columns and entry slot (bit l: the entry of column 64 g + l is -)
+    uint16_t *dn_idx16 = nullptr;
+    uint64_t *dn_sgn64 = nullptr;
     // up table for the blocked slab pass: rows are grouped in blocks of equal
     // occupation of the top sites; per row the hops that stay in the block come
     // first (block-local row | sign<<31), then the others (row | sign<<31)
@@ -131,6 +139,8 @@ struct HvArgs {
     int dn_ngroups;
     const uint4 *dn_groups16;  // null when rows exceed 32767 elements
     const uint8_t *dn_nq8;
+    const uint4 *dn_idx16 = nullptr;      // FP64 row-pass indices (null: not built)
+    const uint64_t *dn_sgn64 = nullptr;   // their signs, per 64 columns and slot
     const uint32_t *up_blk;
     const uint16_t *up_nint, *up_next;
     const int32_t *up_bstart;
