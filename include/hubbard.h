@@ -243,6 +243,21 @@ int hubbard_lowest_states(hubbard_h h, int k, const hubbard_opts *opts, double *
  * Synchronous on the handle's stream. */
 int hubbard_observables(hubbard_h h, const double *psi, double *dens, double *corr, double *docc);
 
+/* hubbard_observables for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and errors, with no hipMalloc,
+ * hipFree or other allocating call.  The partial sums live in a static device
+ * array of 16 MiB per device, held from the first call on that device until
+ * the process ends; lattices whose partial sums would not fit it (none for the
+ * workgroup counts used here) return ERANGE.  With more than 16 sites the
+ * accumulation runs on fewer workgroups than hubbard_observables uses, so the
+ * sums are added in another order (equal within FP64 rounding); with at most
+ * 16 sites they are bitwise equal.  Every call on a device shares that
+ * device's array: calls that overlap on one device (two streams, two host
+ * threads) race and must be serialised by the caller.  Synchronous on the
+ * handle's stream. */
+int hubbard_observables_noalloc(hubbard_h h, const double *psi, double *dens, double *corr, double *docc);
+
 /* Result of hubbard_propagate. */
 typedef struct {
     double err_est;          /* sum over the steps of |psi| b_{m+1} |(exp(-i T_m dt) e_1)_m|: the Lanczos

@@ -124,6 +124,7 @@ def _load():
         "hubbard_lanczos_batch": [vp, i32, ctypes.POINTER(hubbard_opts), ctypes.POINTER(hubbard_result)],
         "hubbard_lowest_states": [vp, i32, ctypes.POINTER(hubbard_opts), vp, vp, ctypes.POINTER(hubbard_result)],
         "hubbard_observables": [vp, vp, vp, vp, vp],
+        "hubbard_observables_noalloc": [vp, vp, vp, vp, vp],
         "hubbard_propagate": [vp, vp, vp, dbl, i32, i32, vp, ctypes.POINTER(hubbard_prop_result)],
         "hubbard_server_create": [ctypes.c_size_t, i32, ctypes.POINTER(vp)],
         "hubbard_server_submit": [vp, ctypes.POINTER(hubbard_request), ctypes.POINTER(ctypes.c_uint64)],
@@ -384,6 +385,20 @@ def hubbard_observables(h: Handle, psi, stream="current") -> dict:
     d = ctypes.c_double()
     _check(_lib.hubbard_observables(h, _dev_ptr(psi, "float64", h.dim, "psi"), dens.ctypes.data, corr.ctypes.data,
                                     ctypes.byref(d)), "hubbard_observables")
+    return {"dens": dens.reshape(2, n), "corr": corr.reshape(3, n, n), "docc": d.value}
+
+
+def hubbard_observables_noalloc(h: Handle, psi, stream="current") -> dict:
+    """hubbard_observables through the entry point that allocates no device
+    memory (partial sums in the library's static per-device scratch)."""
+    if stream == "current":
+        hubbard_set_stream(h, _current_stream())
+    n = h.sites
+    dens = np.zeros(2 * n)
+    corr = np.zeros(3 * n * n)
+    d = ctypes.c_double()
+    _check(_lib.hubbard_observables_noalloc(h, _dev_ptr(psi, "float64", h.dim, "psi"), dens.ctypes.data,
+                                            corr.ctypes.data, ctypes.byref(d)), "hubbard_observables_noalloc")
     return {"dens": dens.reshape(2, n), "corr": corr.reshape(3, n, n), "docc": d.value}
 
 

@@ -1179,6 +1179,62 @@ int hubbard_lowest_states(hubbard_h h, int k, const hubbard_opts *opts, double *
     });
 }
 
+// The normalised observables from the unnormalised device sums r (host copy).
+static void observables_out(const hubbard *h, const double *r, double *dens, double *corr, double *docc)
+{
+    const int NS = obs_ns_max(h->sites);
+    const double norm = r[(size_t)3 * NS * NS];
+    if (!(norm > 0.0) || !std::isfinite(norm))
+        fail(HUBBARD_EINVAL, "psi has zero or non-finite norm");
+    const int n = h->sites;
+    auto at = [&](int block, int i, int j) { return r[(size_t)block * NS * NS + (size_t)i * NS + j] / norm; };
+    if (dens)
+        for (int i = 0; i < n; i++) {
+            dens[i] = at(0, i, i);
+            dens[n + i] = at(1, i, i);
+        }
+    if (corr)
+        for (int b = 0; b < 3; b++)
+            for (int i = 0; i < n; i++)
+                for (int j = 0; j < n; j++)
+                    corr[(size_t)b * n * n + (size_t)i * n + j] = at(b, i, j);
+    if (docc) {
+        double d = 0.0;
+        for (int i = 0; i < n; i++)
+            d += r[(size_t)2 * NS * NS + (size_t)i * NS + i];
+        *docc = d / norm;
+    }
+}
+
+int hubbard_observables_noalloc(hubbard_h h, const double *psi, double *dens, double *corr, double *docc)
+{
+    return guarded([&]() -> int {
+        check_handle(h);
+        if (!psi)
+            fail(HUBBARD_EINVAL, "psi is NULL");
+        use_device(h);
+        const int NS = obs_ns_max(h->sites);
+        const int ps = 3 * NS * NS + 1;
+        double *scr = obs_scratch(h->device);
+        const int nb = obs_noalloc_blocks(h->sites, h->up.dim, h->dn.dim);
+        const int np = obs_partial_count(h->sites, h->up.dim, h->dn.dim, nb);
+        if ((size_t)(np + 1) * (size_t)ps * sizeof(double) > kObsScratchBytes)
+            fail(HUBBARD_ERANGE, "the partial sums of this lattice exceed the " +
+                                     std::to_string(kObsScratchBytes >> 20) + " MiB observables scratch");
+        // partials first, the final sums after them; every value is written
+        // by the kernels before it is read, so nothing is cleared
+        double *part = scr, *sums = scr + (size_t)np * (size_t)ps;
+        launch_observables(psi, h->dev.states_up, h->dev.states_dn, h->sites, h->up.dim, h->dn.dim, part, sums, nb,
+                           h->stream);
+        // host copy of the sums in a buffer of this thread (no allocation per call)
+        thread_local double r[3 * 32 * 32 + 1];
+        HUB_HIP(hipMemcpyAsync(r, sums, sizeof(double) * (size_t)ps, hipMemcpyDeviceToHost, h->stream));
+        HUB_HIP(hipStreamSynchronize(h->stream));
+        observables_out(h, r, dens, corr, docc);
+        return HUBBARD_OK;
+    });
+}
+
 int hubbard_observables(hubbard_h h, const double *psi, double *dens, double *corr, double *docc)
 {
     return guarded([&]() -> int {
@@ -1192,31 +1248,11 @@ int hubbard_observables(hubbard_h h, const double *psi, double *dens, double *co
         DevBuf part(sizeof(double) * (size_t)np * (size_t)ps);
         DevBuf sums(sizeof(double) * (size_t)ps);
         launch_observables(psi, h->dev.states_up, h->dev.states_dn, h->sites, h->up.dim, h->dn.dim,
-                           part.as<double>(), sums.as<double>(), h->stream);
+                           part.as<double>(), sums.as<double>(), kObsDefaultBlocks, h->stream);
         std::vector<double> r((size_t)ps);
         HUB_HIP(hipMemcpyAsync(r.data(), sums.p, sizeof(double) * (size_t)ps, hipMemcpyDeviceToHost, h->stream));
         HUB_HIP(hipStreamSynchronize(h->stream));
-        const double norm = r[(size_t)3 * NS * NS];
-        if (!(norm > 0.0) || !std::isfinite(norm))
-            fail(HUBBARD_EINVAL, "psi has zero or non-finite norm");
-        const int n = h->sites;
-        auto at = [&](int block, int i, int j) { return r[(size_t)block * NS * NS + (size_t)i * NS + j] / norm; };
-        if (dens)
-            for (int i = 0; i < n; i++) {
-                dens[i] = at(0, i, i);
-                dens[n + i] = at(1, i, i);
-            }
-        if (corr)
-            for (int b = 0; b < 3; b++)
-                for (int i = 0; i < n; i++)
-                    for (int j = 0; j < n; j++)
-                        corr[(size_t)b * n * n + (size_t)i * n + j] = at(b, i, j);
-        if (docc) {
-            double d = 0.0;
-            for (int i = 0; i < n; i++)
-                d += r[(size_t)2 * NS * NS + (size_t)i * NS + i];
-            *docc = d / norm;
-        }
+        observables_out(h, r.data(), dens, corr, docc);
         return HUBBARD_OK;
     });
 }

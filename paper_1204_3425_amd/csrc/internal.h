@@ -221,11 +221,19 @@ void launch_reduce(const double *partials, int n, int stride, int count, double 
 // observables.hip: unnormalised sums UU, DD, C (NS x NS each, NS = obs_ns_max)
 // and the norm of psi^2 into out[3 * NS * NS + 1]; part holds
 // obs_partial_count blocks of that size (the workgroups' partials and the
-// group sums of the reduction).
+// group sums of the reduction).  max_blocks bounds the accumulating workgroups.
+constexpr int kObsDefaultBlocks = 2048;
 int obs_ns_max(int sites);
-int obs_partial_count(int ns, int64_t dim_up, int64_t dim_dn);
+int obs_partial_count(int ns, int64_t dim_up, int64_t dim_dn, int max_blocks = kObsDefaultBlocks);
 void launch_observables(const double *psi, const uint32_t *states_up, const uint32_t *states_dn, int ns,
-                        int64_t dim_up, int64_t dim_dn, double *part, double *out, hipStream_t s);
+                        int64_t dim_up, int64_t dim_dn, double *part, double *out, int max_blocks, hipStream_t s);
+// The allocation-free form: a static device array of kObsScratchBytes per
+// device (its address taken once per device), and the largest workgroup count
+// whose partial sums fit it.
+constexpr size_t kObsScratchBytes = (size_t)16 << 20;
+constexpr int kObsMaxDevices = 64;
+double *obs_scratch(int device);
+int obs_noalloc_blocks(int ns, int64_t dim_up, int64_t dim_dn);
 
 // propagate.hip: the Krylov propagation step (see the file's header for the
 // slot layout and the device scalars sc[4j..4j+3] = {s_j, 0, a_j, b_{j+1}})

@@ -20,6 +20,9 @@
 // so the result is reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "internal.h"
 
 // wave-wide sum from the ROCm device library (DPP reduction, every lane gets it)
@@ -237,11 +240,11 @@ __global__ __launch_bounds__(256) void obs_sum_groups_kernel(const double *__res
 
 int obs_ns_max(int sites) { return sites <= 16 ? 16 : 32; }
 
-static void obs_grid(int ns, int64_t dim_up, int64_t dim_dn, int &ntiles, int &nchunks)
+static void obs_grid(int ns, int64_t dim_up, int64_t dim_dn, int &ntiles, int &nchunks, int max_blocks = 2048)
 {
     const int tw = kObsSlots * (ns <= 16 ? obs_threads<16>() : obs_threads<32>());
     ntiles = (int)((dim_dn + tw - 1) / tw);
-    int64_t nc = 2048 / ntiles;
+    int64_t nc = max_blocks / ntiles;
     if (nc < 1)
         nc = 1;
     if (nc > dim_up)
@@ -249,19 +252,19 @@ static void obs_grid(int ns, int64_t dim_up, int64_t dim_dn, int &ntiles, int &n
     nchunks = (int)nc;
 }
 
-int obs_partial_count(int ns, int64_t dim_up, int64_t dim_dn)
+int obs_partial_count(int ns, int64_t dim_up, int64_t dim_dn, int max_blocks)
 {
     int ntiles, nchunks;
-    obs_grid(ns, dim_up, dim_dn, ntiles, nchunks);
+    obs_grid(ns, dim_up, dim_dn, ntiles, nchunks, max_blocks);
     return ntiles * nchunks + kObsGroups;  // the workgroups' partials, then the group sums
 }
 
 template <int NS>
 static void launch_obs(const double *psi, const uint32_t *states_up, const uint32_t *states_dn, int ns, int64_t dim_up,
-                       int64_t dim_dn, double *part, double *out, hipStream_t s)
+                       int64_t dim_dn, double *part, double *out, int max_blocks, hipStream_t s)
 {
     int ntiles, nchunks;
-    obs_grid(ns, dim_up, dim_dn, ntiles, nchunks);
+    obs_grid(ns, dim_up, dim_dn, ntiles, nchunks, max_blocks);
     const int nblocks = ntiles * nchunks;
     constexpr int TW = obs_threads<NS>();
     hipLaunchKernelGGL((obs_accumulate_kernel<NS, TW>), dim3(nblocks), dim3(TW), 0, s, psi, states_up, states_dn, ns,
@@ -276,12 +279,49 @@ static void launch_obs(const double *psi, const uint32_t *states_up, const uint3
 }
 
 void launch_observables(const double *psi, const uint32_t *states_up, const uint32_t *states_dn, int ns,
-                        int64_t dim_up, int64_t dim_dn, double *part, double *out, hipStream_t s)
+                        int64_t dim_up, int64_t dim_dn, double *part, double *out, int max_blocks, hipStream_t s)
 {
     if (ns <= 16)
-        launch_obs<16>(psi, states_up, states_dn, ns, dim_up, dim_dn, part, out, s);
+        launch_obs<16>(psi, states_up, states_dn, ns, dim_up, dim_dn, part, out, max_blocks, s);
     else
-        launch_obs<32>(psi, states_up, states_dn, ns, dim_up, dim_dn, part, out, s);
+        launch_obs<32>(psi, states_up, states_dn, ns, dim_up, dim_dn, part, out, max_blocks, s);
+}
+
+// Scratch of the entry point that allocates nothing (hubbard_observables_noalloc):
+// the workgroups' partial sums, their group sums and the final sums live in this
+// array, one copy per device for the life of the process.  Host code never
+// passes the array's name to a kernel: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) double scratch[kObsScratchBytes / sizeof(double)];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kObsMaxDevices] = {};
+
+double *obs_scratch(int device)
+{
+    if (device < 0 || device >= kObsMaxDevices)
+        fail(HUBBARD_EDEVICE, "device index out of range for the observables scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(HUBBARD_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    return static_cast<double *>(g_scratch_ptr[device]);
+}
+
+int obs_noalloc_blocks(int ns, int64_t dim_up, int64_t dim_dn)
+{
+    const int ps = ns <= 16 ? obs_partial_size<16>() : obs_partial_size<32>();
+    // partials (blocks + groups) and the final sums must fit the scratch
+    const int64_t cap = (int64_t)(kObsScratchBytes / sizeof(double)) / ps - kObsGroups - 1;
+    int max_blocks = (int)std::min<int64_t>(2048, cap);
+    while (max_blocks > 1 && (int64_t)(obs_partial_count(ns, dim_up, dim_dn, max_blocks) + 1) * ps >
+                                 (int64_t)(kObsScratchBytes / sizeof(double)))
+        max_blocks--;
+    return max_blocks;
 }
 
 }  // namespace hub
