@@ -1,12 +1,13 @@
 // Host side of the batched Lanczos engine (kernels in batch.hip).
 //
 // Each call to step() advances every active instance by one step of Alg. 1
-// (Sec. 2.2) with four launches.  The step's last kernel computes E_j and the
-// stop test on the device and writes every instance's {a_j, b_{j+1}, E_j,
-// code} to a mailbox; the host copies the mailboxes back asynchronously and
-// reads them kLookahead steps behind, so it never waits for the device inside
-// a run.  Stopped instances skip later steps; the descriptor table is rebuilt
-// when instances join or when every listed one has finished.
+// (Sec. 2.2) with two launches.  The first launch of step j also computes
+// E_{j-1} and the stop test of step j - 1 on the device and writes every
+// instance's {a_{j-1}, b_j, E_{j-1}, code} to a mailbox in mapped host memory;
+// the host reads them kLookahead steps behind (after that step's event), so it
+// never waits for the device inside a run.  Stopped instances skip later
+// steps; the descriptor table is rebuilt when instances join or when every
+// listed one has finished.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -31,9 +32,16 @@ struct Dev {
     Dev &operator=(const Dev &) = delete;
 };
 
+// Pinned host memory that kernels write directly (mapped, coherent): the
+// mailboxes reach the host with no copy in the stream.
 struct Pinned {
     void *p = nullptr;
-    explicit Pinned(size_t bytes) { HUB_HIP(hipHostMalloc(&p, bytes ? bytes : 16, hipHostMallocDefault)); }
+    void *dev = nullptr;  // the same memory's device address
+    explicit Pinned(size_t bytes)
+    {
+        HUB_HIP(hipHostMalloc(&p, bytes ? bytes : 16, hipHostMallocMapped | hipHostMallocCoherent));
+        HUB_HIP(hipHostGetDevicePointer(&dev, p, 0));
+    }
     ~Pinned()
     {
         if (p)
@@ -56,9 +64,14 @@ struct Slot {
     hubbard *h = nullptr;
     hubbard_opts o{};
     hubbard_result *res = nullptr;
-    std::unique_ptr<Dev> work, state, part, hist;
+    std::unique_ptr<Dev> mem;  // the instance's buffers, carved from one allocation
+    void *work = nullptr;
+    BatchState *state = nullptr;
+    double *part = nullptr, *part2 = nullptr, *hist = nullptr;
     int64_t rpi = 1;
     int nitems = 0;
+    int64_t launched = 0;  // steps launched for this instance
+    int norm_at = -1;      // pending start vector: index of its squared norm in the host array
     int index = -1;  // position in the current descriptor table, -1 before the first rebuild
     std::vector<double> a, b, e;
     int stop = HUBBARD_STOP_MAXITER;
@@ -100,26 +113,38 @@ class Engine : public BatchRunner {
         sl->res = res;
         sl->t0 = std::chrono::steady_clock::now();
         const int64_t n = h->dim;
-        sl->work = std::make_unique<Dev>(2 * sizeof(T) * (size_t)n);
-        sl->state = std::make_unique<Dev>(sizeof(BatchState));
-        sl->hist = std::make_unique<Dev>(sizeof(double) * 2 * (size_t)o.max_iter);
         sl->rpi = rows_per_item(h);
         sl->nitems = (int)((h->up.dim + sl->rpi - 1) / sl->rpi);
         const int sb = stream_blocks(n);
-        sl->part = std::make_unique<Dev>(sizeof(double) * (size_t)std::max(sl->nitems, 2 * sb + 8));
-        // f_1 from the seed (or the given vector), normalised in FP64 (Alg. 1)
-        double *part = static_cast<double *>(sl->part->p);
-        BatchState *st = static_cast<BatchState *>(sl->state->p);
-        launch_start_norm2(o.start, o.seed, n, part, sb, s_);
-        launch_reduce(part, sb, 0, 1, st->S + 4, s_);
-        double nrm2 = 0.0;
-        HUB_HIP(hipMemcpyAsync(&nrm2, st->S + 4, sizeof(double), hipMemcpyDeviceToHost, s_));
-        HUB_HIP(hipStreamSynchronize(s_));
-        if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
-            fail(HUBBARD_EINVAL, "start vector has zero or non-finite norm");
-        T *v0 = static_cast<T *>(sl->work->p);
-        launch_start_fill<T>(o.start, o.seed, 1.0 / std::sqrt(nrm2), v0, v0 + n, h->up.dim, h->dn.dim, h->dn.dim, s_);
-        launch_batch_init_state(st, s_);
+        // one allocation: the two vectors, the state, the coefficient history
+        // and both sets of partial sums, each on 256 bytes
+        auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t b_work = up(2 * sizeof(T) * (size_t)n), b_state = up(sizeof(BatchState)),
+                     b_hist = up(sizeof(double) * 2 * (size_t)o.max_iter),
+                     b_part = up(sizeof(double) * (size_t)std::max(sl->nitems, 2 * sb + 8)),
+                     b_part2 = up(sizeof(double) * (size_t)sl->nitems);
+        sl->mem = std::make_unique<Dev>(b_work + b_state + b_hist + b_part + b_part2);
+        char *base = static_cast<char *>(sl->mem->p);
+        sl->work = base;
+        sl->state = reinterpret_cast<BatchState *>(base + b_work);
+        sl->hist = reinterpret_cast<double *>(base + b_work + b_state);
+        sl->part = reinterpret_cast<double *>(base + b_work + b_state + b_hist);
+        sl->part2 = reinterpret_cast<double *>(base + b_work + b_state + b_hist + b_part);
+        // |f_1|^2 from the seed (or the given vector), written straight to host
+        // memory; the start vector is filled once all joining instances' norms
+        // are known (one wait for all of them)
+        if (norms_cap_ <= pending_fill_) {
+            // grow before any pending norm is written: the array is only swapped while none is
+            (void)hipStreamSynchronize(s_);
+            std::unique_ptr<Pinned> bigger = std::make_unique<Pinned>(sizeof(double) * (size_t)(2 * norms_cap_ + 64));
+            if (norms_ && pending_fill_ > 0)
+                std::memcpy(bigger->p, norms_->p, sizeof(double) * (size_t)pending_fill_);
+            norms_ = std::move(bigger);
+            norms_cap_ = 2 * norms_cap_ + 64;
+        }
+        sl->norm_at = pending_fill_++;
+        launch_start_norm2(o.start, o.seed, n, sl->part, sb, s_);
+        launch_reduce(sl->part, sb, 0, 1, static_cast<double *>(norms_->dev) + sl->norm_at, s_);
         slots_.push_back(std::move(sl));
         dirty_ = true;
     }
@@ -138,11 +163,11 @@ class Engine : public BatchRunner {
             return finished;
         if (pending_stopped_ < (int)table_.size()) {
             const int k = (int)(launched_ % kRing);
-            double *mb = static_cast<double *>(mail_->p) + (size_t)k * 4 * table_.size();
+            double *mb = static_cast<double *>(mail_host_->dev) + (size_t)k * 4 * table_.size();
             launch_batch_step<T>(static_cast<BatchInst *>(insts_->p), (int)table_.size(),
-                                 static_cast<const BatchItem *>(items_->p), n_items_, lds_, mb, s_);
-            double *mh = static_cast<double *>(mail_host_->p) + (size_t)k * 4 * table_.size();
-            HUB_HIP(hipMemcpyAsync(mh, mb, sizeof(double) * 4 * table_.size(), hipMemcpyDeviceToHost, s_));
+                                 static_cast<const BatchItem *>(items_->p), n_items_, lds_, mb, (int)launched_, s_);
+            for (Slot<T> *sl : table_)
+                sl->launched++;
             HUB_HIP(hipEventRecord(ev_[k], s_));
             launched_++;
         }
@@ -170,7 +195,7 @@ class Engine : public BatchRunner {
             if (sl.done)
                 continue;
             const double code = mb[4 * i + 3];
-            if (code == kMailStopped)
+            if (code == kMailStopped || code == kMailNone)
                 continue;
             if (code == kMailBad)
                 fail(HUBBARD_EDEVICE, "non-finite Lanczos coefficient in a batched solve");
@@ -223,6 +248,23 @@ class Engine : public BatchRunner {
         HUB_HIP(hipStreamSynchronize(s_));
         while (read_ < launched_)
             read_step(finished);
+        // start vectors of the instances that joined: f_1 = f / |f| (Alg. 1)
+        const double *nh = norms_ ? static_cast<const double *>(norms_->p) : nullptr;
+        for (auto &slp : slots_) {
+            Slot<T> &sl = *slp;
+            if (sl.norm_at < 0)
+                continue;
+            const double nrm2 = nh[sl.norm_at];
+            sl.norm_at = -1;
+            if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+                fail(HUBBARD_EINVAL, "start vector has zero or non-finite norm");
+            const hubbard *h = sl.h;
+            T *v0 = static_cast<T *>(sl.work);
+            launch_start_fill<T>(sl.o.start, sl.o.seed, 1.0 / std::sqrt(nrm2), v0, v0 + h->dim, h->up.dim, h->dn.dim,
+                                 h->dn.dim, s_);
+            launch_batch_init_state(sl.state, s_);
+        }
+        pending_fill_ = 0;
         std::vector<std::unique_ptr<Slot<T>>> keep;
         for (auto &sl : slots_)
             if (!sl->done)
@@ -256,16 +298,18 @@ class Engine : public BatchRunner {
             d.w_dn = h->dn.width;
             d.t = h->t;
             d.U = h->U;
-            T *v0 = static_cast<T *>(sl.work->p);
+            T *v0 = static_cast<T *>(sl.work);
             d.vec0 = v0;
             d.vec1 = v0 + h->dim;
-            d.st = static_cast<BatchState *>(sl.state->p);
-            d.hist = static_cast<double *>(sl.hist->p);
-            d.part = static_cast<double *>(sl.part->p);
+            d.st = sl.state;
+            d.hist = sl.hist;
+            d.part = sl.part;
+            d.part2 = sl.part2;
             d.tol = sl.o.tol;
             d.nparts = sl.nitems;
             d.slot = i;
             d.max_iter = sl.o.max_iter;
+            d.j0 = (int32_t)sl.launched;
             sl.index = i;
             for (int k = 0; k < sl.nitems; k++) {
                 BatchItem it;
@@ -281,7 +325,6 @@ class Engine : public BatchRunner {
         if (!insts_ || insts_cap_ < (size_t)n) {
             insts_cap_ = (size_t)n * 2;
             insts_ = std::make_unique<Dev>(sizeof(BatchInst) * insts_cap_);
-            mail_ = std::make_unique<Dev>(sizeof(double) * 4 * insts_cap_ * kRing);
             mail_host_ = std::make_unique<Pinned>(sizeof(double) * 4 * insts_cap_ * kRing);
         }
         if (!items_ || items_cap_ < items.size()) {
@@ -298,8 +341,10 @@ class Engine : public BatchRunner {
     hipStream_t s_;
     std::vector<std::unique_ptr<Slot<T>>> slots_;
     std::vector<Slot<T> *> table_;  // the instances of the current descriptor table, in slot order
-    std::unique_ptr<Dev> insts_, items_, mail_;
+    std::unique_ptr<Dev> insts_, items_;
     std::unique_ptr<Pinned> mail_host_;
+    std::unique_ptr<Pinned> norms_;  // squared start norms of joining instances (written by the device)
+    int norms_cap_ = 0, pending_fill_ = 0;
     hipEvent_t ev_[kRing];
     size_t insts_cap_ = 0, items_cap_ = 0, lds_ = 16;
     int n_items_ = 0;
@@ -323,7 +368,7 @@ size_t batch_vector_bytes(const hubbard *h, int precision)
     const int64_t rpi = rows_per_item(h);
     const int64_t items = (h->up.dim + rpi - 1) / rpi;
     return 2 * es * (size_t)h->dim + 8 * sizeof(double) +
-           sizeof(double) * (size_t)std::max<int64_t>(items, 2 * stream_blocks(h->dim) + 8);
+           sizeof(double) * (size_t)(std::max<int64_t>(items, 2 * stream_blocks(h->dim) + 8) + items);
 }
 
 bool batchable(const hubbard *h, int precision)

@@ -8,16 +8,17 @@
 
 namespace hub {
 
-// Per-instance state that the batched kernels update in place (device memory,
-// owned by the instance; descriptors stay read-only between rebuilds).
+// Per-instance state (device memory, owned by the instance; descriptors stay
+// read-only between rebuilds).  The step's scalars are not kept here: every
+// workgroup derives them from the recorded coefficients and partial sums.
 struct BatchState {
-    double S[8];     // {1/s of the current vector, alpha, beta, c, -, -, a_j, b_{j+1}}
+    double S[8];     // S[4]: squared norm of the start vector (set up by the host path)
     double scale;    // running max_k |a_k| + b_k (breakdown test)
     double e_prev;   // Ritz value of the previous step
     double e_prev2;  // and of the step before
-    int32_t j;       // steps done
-    int32_t stopped; // set by the step that stops the instance
-    int32_t cur;     // 0: vec0 holds s f_j, 1: vec1 does
+    int32_t j;       // steps whose coefficients are recorded
+    int32_t stopped; // set when the stop test of a step fires
+    int32_t cur;     // unused (the vector roles follow the step's parity)
     int32_t pad_;
 };
 
@@ -31,21 +32,24 @@ struct BatchInst {
     void *vec0, *vec1;  // the two Lanczos vectors, dense rows
     BatchState *st;
     double *hist;       // a_{k+1} at 2k, b_{k+2} at 2k + 1
-    double *part;       // partial sums, one per work item of this instance
+    double *part;       // H.v partial sums (y.x), one per work item of this instance
+    double *part2;      // update partial sums (|q|^2), one per work item
     double tol;
     int32_t nparts;
     int32_t slot;       // mailbox slot
     int32_t max_iter;
-    int32_t pad_;
+    int32_t j0;         // steps launched for this instance before the table was built
 };
 
-// Mailbox entry written by the step's last kernel for every instance:
-// {a_j, b_{j+1}, E_j, code}; code = -1 running, a HUBBARD_STOP_* value when
-// this step stops the instance, kMailStopped when it had stopped before,
-// kMailBad when a coefficient is not finite.
+// Mailbox entry for every instance, written by the launch that computes the
+// Ritz value of the step before (the first launch of step j reports step
+// j - 1): {a, b, E, code}; code = -1 running, a HUBBARD_STOP_* value when that
+// step stops the instance, kMailStopped when it had stopped before, kMailBad
+// when a coefficient is not finite, kMailNone when there is no step before.
 constexpr double kMailRunning = -1.0;
 constexpr double kMailStopped = -2.0;
 constexpr double kMailBad = -3.0;
+constexpr double kMailNone = -4.0;
 
 // A work item: rows [r0, r0 + nrows) of instance `inst`, writing partial `part`.
 struct BatchItem {
@@ -55,9 +59,12 @@ struct BatchItem {
     int64_t nrows;
 };
 
+// One Lanczos step j of every active instance in two launches: the H.v with
+// the three-term update (and, in extra workgroups, the Ritz value and stop
+// test of step j - 1), then the q - a_j f_j update with its norm.
 template <typename T>
 void launch_batch_step(BatchInst *insts_dev, int n_inst, const BatchItem *items_dev, int n_items, size_t lds_bytes,
-                       double *mailbox_dev, hipStream_t s);
+                       double *mailbox_dev, int j, hipStream_t s);
 
 // zeroes an instance's state and sets S = {1, 1, 0, 0} (f_1 has scale 1, b_1 = 0)
 void launch_batch_init_state(BatchState *st, hipStream_t s);

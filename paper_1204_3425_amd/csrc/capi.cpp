@@ -79,9 +79,16 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned host memory, mapped and coherent: kernels may write it directly
+// (through dev), and the host reads it once the writing work has completed.
 struct PinnedBuf {
     void *p = nullptr;
-    explicit PinnedBuf(size_t bytes) { HUB_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault)); }
+    void *dev = nullptr;
+    explicit PinnedBuf(size_t bytes)
+    {
+        HUB_HIP(hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+        HUB_HIP(hipHostGetDevicePointer(&dev, p, 0));
+    }
     ~PinnedBuf()
     {
         if (p)
@@ -438,9 +445,10 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     DevBuf scal(sizeof(double) * (8 + kMaxDeflate + 1) + sizeof(double) * 2 * (size_t)(max_iter + 1));
     double *S = scal.as<double>();
     double *D = S + 8;  // projections psi_l . q of the deflated step
-    double *hist = D + kMaxDeflate + 1;
     PinnedBuf host(sizeof(double) * (2 * (size_t)(max_iter + 1) + 8));
     double *hh = host.as<double>();
+    // the reductions write a_j, b_{j+1} straight to host memory (no copy per step)
+    double *hist = static_cast<double *>(host.dev);
     const double *given = o.start;
     const uint64_t seed = o.seed;
 
@@ -593,7 +601,6 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
                 keep(C, j0);
                 step(C, P, j0);
             }
-            HUB_HIP(hipMemcpyAsync(hh + 2 * j0, hist + 2 * j0, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
             HUB_HIP(hipEventRecord(ev[(size_t)(j0 % nev)], s));
             launched++;
         }

@@ -43,7 +43,8 @@ struct Job {
 // blocked entries, the entry lines: one 128-byte line per row when a row has
 // at most 32 hops, two when it has at most 64, none beyond; counts, states)
 // and down side (column-major entries, 64- and 32-bit offset groups, 16-bit
-// groups, counts, states).
+// groups, counts, states, and the FP64 row pass's 16-bit indices and sign
+// words).
 size_t footprint(const hubbard_request &r)
 {
     const uint64_t du = binomial(r.sites, r.n_up), dd = binomial(r.sites, r.n_dn);
@@ -53,7 +54,8 @@ size_t footprint(const hubbard_request &r)
     const size_t w = (size_t)std::max(1, r.n_edges);
     const size_t lines = w <= 32 ? 128 : (w <= 64 ? 256 : 0);
     const size_t up = (size_t)du * (8 * w + 14 + lines);
-    const size_t dn = (size_t)dd * (14 * w + 56);
+    const size_t g8 = (w + 7) / 8;  // groups of eight entries per column
+    const size_t dn = (size_t)dd * (14 * w + 56 + 16 * g8 + g8);
     return vecs + up + dn;
 }
 
