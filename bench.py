@@ -111,6 +111,28 @@ def time_hv(hb, torch, h, precision, launches, warmup, median=False):
     return e0.elapsed_time(e1) / launches * 1e-3
 
 
+def time_hv_dense(hb, torch, h, precision, launches, warmup):
+    """Mean time of hubbard_apply on the caller's dense J-order vectors (rows of
+    dim_dn elements, no padding), from HIP events on the kernels' stream."""
+    hb.hubbard_set_precision(h, precision)
+    dt = torch.float64 if precision == hb.HUBBARD_FP64 else torch.float32
+    f = torch.empty(h.dim, dtype=torch.float64, device="cuda:0")
+    hb.hubbard_start_raw(12043425, h.dim, f)
+    x = f.to(dt)
+    del f
+    y = torch.empty_like(x)
+    for _ in range(warmup):
+        hb.hubbard_apply(h, x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        hb.hubbard_apply(h, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / launches * 1e-3
+
+
 def time_lanczos(hb, torch, h, precision, steps, warmup, seed):
     if warmup:
         hb.hubbard_lanczos_ex(h, tol=-1.0, max_iter=warmup, precision=precision, seed=seed, history=False)
@@ -792,9 +814,10 @@ def main():
     for name, prec, es in (("fp64", hb.HUBBARD_FP64, 8), ("mixed", hb.HUBBARD_MIXED, 4)):
         log("timing H.v", name)
         t_hv = time_hv(hb, torch, h, prec, max(10, args.steps // 4), 3)
+        t_dense = time_hv_dense(hb, torch, h, prec, max(10, args.steps // 4), 3)
         log("timing Lanczos", name, args.steps, "steps")
         t_lz, r = time_lanczos(hb, torch, h, prec, args.steps, args.warmup, p.seed)
-        res[name] = {"hv_s": t_hv, "hv_gbs": 2.0 * p.dim * es / t_hv / 1e9, "lanczos_s": t_lz,
+        res[name] = {"hv_s": t_hv, "hv_dense_s": t_dense, "hv_gbs": 2.0 * p.dim * es / t_hv / 1e9, "lanczos_s": t_lz,
                      "iters": r["n_iter"], "E0": r["E0"]}
         log(name, "H.v %.1f us (%.0f GB/s)" % (t_hv * 1e6, res[name]["hv_gbs"]),
             "Lanczos %.3f ms/iter, E0 %.12f" % (t_lz / r["n_iter"] * 1e3, r["E0"]))
@@ -829,6 +852,7 @@ def main():
         "lanczos_iters_per_s": {k: round(v["iters"] / v["lanczos_s"], 2) for k, v in res.items()},
         "lanczos_ms_per_iter": {k: round(v["lanczos_s"] / v["iters"] * 1e3, 4) for k, v in res.items()},
         "hv_us": {k: round(v["hv_s"] * 1e6, 1) for k, v in res.items()},
+        "hv_dense_apply_us": {k: round(v["hv_dense_s"] * 1e6, 1) for k, v in res.items()},
         "hv_gbs": {k: round(v["hv_gbs"], 1) for k, v in res.items()},
         "E0": {k: v["E0"] for k, v in res.items()},
         "E0_rel_err_vs_oracle": e0_err,

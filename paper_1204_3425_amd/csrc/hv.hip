@@ -27,9 +27,10 @@
 // hops that stay inside the block; the others read global memory.  Eight
 // lanes cover one row segment with 16-byte accesses, so a wave updates eight
 // rows.  hv_lines_kernel takes a row's entries as one 128-byte line (rows of at
-// most 32 hops); hv_blocks_kernel handles longer rows.  hv_slabs_kernel serves
-// caller buffers whose row stride is not a multiple of 128 bytes.  The running
-// output is read and written with non-temporal accesses.
+// most 32 hops); hv_blocks_kernel handles longer rows.  Rows that start on 16
+// but not on 128 bytes (a caller's dense vector) take the same passes with each
+// XCD on a contiguous range of slabs; hv_slabs_kernel serves rows not on 16
+// bytes.  The running output is read and written with non-temporal accesses.
 //
 // Epilogues (both passes together):
 //   HV_STORE    y = H x
@@ -561,6 +562,7 @@ struct BlockArgs {
     const int32_t *__restrict__ bstart;
     int64_t dim_up, dim_dn;
     int w_up, nblocks, nslab;
+    int contig;  // rows not on 128 bytes: each XCD takes a contiguous range of slabs
     double t;
     double amp[4];
 };
@@ -606,7 +608,10 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
     const int nwave = blockDim.x >> 6;
     const int xcd = blockIdx.x & 7;
     const int local = blockIdx.x >> 3;
-    const int s = (local / p.nblocks) * 8 + xcd;
+    // slab-major per XCD: XCD k takes slabs k, k + 8, ... (rows on 128 bytes),
+    // or the k-th contiguous range of slabs, so that the cache lines two
+    // neighbouring slabs share stay in one L2 (rows not on 128 bytes)
+    const int s = p.contig ? xcd * ((p.nslab + 7) / 8) + local / p.nblocks : (local / p.nblocks) * 8 + xcd;
     const int blk = local % p.nblocks;
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     if (s < p.nslab) {
@@ -756,6 +761,7 @@ struct LineArgs {
     const int32_t *__restrict__ bstart;
     int64_t dim_up, dim_dn;
     int nblocks, nslab;
+    int contig;  // rows not on 128 bytes: each XCD takes a contiguous range of slabs
     double t;
     double amp[4];
 };
@@ -806,7 +812,10 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
     const int nwave = blockDim.x >> 6;
     const int xcd = blockIdx.x & 7;
     const int local = blockIdx.x >> 3;
-    const int s = (local / p.nblocks) * 8 + xcd;
+    // slab-major per XCD: XCD k takes slabs k, k + 8, ... (rows on 128 bytes),
+    // or the k-th contiguous range of slabs, so that the cache lines two
+    // neighbouring slabs share stay in one L2 (rows not on 128 bytes)
+    const int s = p.contig ? xcd * ((p.nslab + 7) / 8) + local / p.nblocks : (local / p.nblocks) * 8 + xcd;
     const int blk = local % p.nblocks;
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     if (s < p.nslab) {
@@ -1211,8 +1220,12 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     else
         launch_rows_rpb<T, 1>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
 
-    const int64_t slw = 128 / (int64_t)sizeof(T);
-    if (pl.blk_grid > 0 && ldx % slw == 0 && ldyr % slw == 0) {
+    // the blocked passes load 16 bytes per lane: rows must start on 16 bytes
+    // (on 128 bytes each row segment is one cache line)
+    const int64_t slw = 128 / (int64_t)sizeof(T), v16 = 16 / (int64_t)sizeof(T);
+    const bool on16 = ldx % v16 == 0 && ldyr % v16 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)yr % 16 == 0;
+    const int contig = (ldx % slw != 0 || ldyr % slw != 0) ? 1 : 0;
+    if (pl.blk_grid > 0 && on16) {
         BlockArgs ba;
         ba.ent = a.up_blk;
         ba.nint = a.up_nint;
@@ -1223,6 +1236,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
         ba.w_up = a.w_up > 0 ? a.w_up : 1;
         ba.nblocks = a.up_nblocks;
         ba.nslab = pl.blk_nslab;
+        ba.contig = contig;
         ba.t = a.t;
         for (int c = 0; c < 4; c++)
             ba.amp[c] = a.amp4[c];
@@ -1243,6 +1257,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             la.dim_dn = a.dim_dn;
             la.nblocks = a.up_nblocks;
             la.nslab = pl.blk_nslab;
+            la.contig = contig;
             la.t = a.t;
             const bool w64 = a.up_line_w == 64;
             for (int c = 0; c < 4; c++)
@@ -1280,7 +1295,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
         return pl.blk_grid;
     }
     if (mode == HV_FUSED)
-        fail(HUBBARD_EDEVICE, "fused Lanczos step needs rows aligned to 128 bytes");
+        fail(HUBBARD_EDEVICE, "fused Lanczos step needs rows aligned to 16 bytes");
 
     SlabArgs sa;
     sa.up_rows = a.up_rows;
