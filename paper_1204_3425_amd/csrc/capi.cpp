@@ -104,7 +104,7 @@ static void free_device(hubbard *h)
 {
     DeviceTables &d = h->dev;
     void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
-                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.dn_idx16, d.dn_sgn64, d.up_blk, d.up_nint, d.up_next,
+                    d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.dn_pidx, d.dn_nidx, d.dn_pn, d.up_blk, d.up_nint, d.up_next,
                     d.up_bstart, d.up_line, d.up_cnt, d.tcls};
     for (void *p : ptrs)
         if (p)
@@ -185,21 +185,53 @@ static void upload_blocked_up(hubbard *h, size_t &total)
         next[(size_t)r] = (uint16_t)ne;
     }
     if (up.width <= 64) {
-        // one 128-byte line of 32 slots per row, or two (64 slots) for rows of 33 to 64 hops
-        const int W = up.width <= 32 ? 32 : 64;
+        // per row group of eight (block rows 8g..8g+7, the rows one wave step
+        // of the line kernel takes): the largest internal and external counts
+        std::vector<uint8_t> gmi((size_t)du), gme((size_t)du);
+        for (int b = 0; b < nb; b++)
+            for (int32_t g0 = bstart[(size_t)b]; g0 < bstart[(size_t)b + 1]; g0 += 8) {
+                const int32_t g1 = std::min(g0 + 8, bstart[(size_t)b + 1]);
+                int mi = 0, me = 0;
+                for (int32_t r = g0; r < g1; r++) {
+                    mi = std::max<int>(mi, nint[(size_t)r]);
+                    me = std::max<int>(me, next[(size_t)r]);
+                }
+                for (int32_t r = g0; r < g1; r++) {
+                    gmi[(size_t)r] = (uint8_t)mi;
+                    gme[(size_t)r] = (uint8_t)me;
+                }
+            }
+        // room to pad: the group's largest internal count and the row's own
+        // external entries must share the row's slots
+        auto pads = [&](int W) {
+            for (int64_t r = 0; r < du; r++)
+                if (gmi[(size_t)r] + next[(size_t)r] > W)
+                    return false;
+            return true;
+        };
+        // one 128-byte line of 32 slots per row, or two (64 slots) for rows of
+        // 33 to 64 hops or where one line has no room for the padding
+        const int W = up.width <= 32 && pads(32) ? 32 : 64;
+        const bool ipad = pads(W);
         std::vector<uint32_t> line((size_t)du * (size_t)W, 0u), cnt((size_t)du);
         for (int64_t r = 0; r < du; r++) {
             const size_t o = (size_t)r * (size_t)w;
             const int ni = nint[(size_t)r], ne = next[(size_t)r];
+            const int b = blk_of[(size_t)r];
             for (int k = 0; k < ni; k++)
                 line[(size_t)r * W + (size_t)k] = ent[o + (size_t)k];
+            if (ipad)
+                for (int k = ni; k < gmi[(size_t)r]; k++)
+                    line[(size_t)r * W + (size_t)k] = (uint32_t)(bstart[(size_t)b + 1] - bstart[(size_t)b]);
             for (int k = 0; k < ne; k++)
                 line[(size_t)r * W + (size_t)(W - 1 - k)] = ent[o + (size_t)(ni + k)];
-            cnt[(size_t)r] = (uint32_t)ni | ((uint32_t)ne << 16);
+            cnt[(size_t)r] = (uint32_t)ni | ((uint32_t)ne << 8) | ((uint32_t)gmi[(size_t)r] << 16) |
+                             ((uint32_t)gme[(size_t)r] << 24);
         }
         d.up_line = upload<uint32_t>(line.data(), line.size() * 4, total);
         d.up_cnt = upload<uint32_t>(cnt.data(), cnt.size() * 4, total);
         d.up_line_w = W;
+        d.up_line_ipad = ipad ? 1 : 0;
     }
     d.up_blk = upload<uint32_t>(ent.data(), ent.size() * 4, total);
     d.up_nint = upload<uint16_t>(nint.data(), nint.size() * 2, total);
@@ -295,24 +327,45 @@ static void upload_tables(hubbard *h)
         d.dn_groups16 = upload<uint16_t>(g.data(), g.size() * 2, total);
         d.dn_nq8 = upload<uint8_t>(nq8.data(), nq8.size(), total);
         if (ddn <= kRow64Max) {
-            // the FP64 row pass: indices alone, signs as one bit per lane of
-            // a 64-column group and entry slot
-            const int64_t ngrp = (ddn + 63) / 64;
-            std::vector<uint16_t> gi((size_t)std::max(ng8, 1) * (size_t)ddn * 8, (uint16_t)ddn);
-            std::vector<uint64_t> sg((size_t)ngrp * (size_t)std::max(ng8, 1) * 8, 0ull);
+            // the FP64 row pass: per column the + hops in groups of eight and
+            // the - hops in groups of four (ascending column order within each)
+            const int64_t nchunk = (ddn + 63) / 64;
+            std::vector<int> np_col((size_t)ddn), nn_col((size_t)ddn);
+            int npm = 1, nnm = 1;
             for (int64_t r = 0; r < ddn; r++) {
-                const int nnz = h->dn.row_nnz[(size_t)r];
-                for (int k = 0; k < nnz; k++) {
-                    size_t src = (size_t)k * (size_t)ddn + (size_t)r;
-                    gi[((size_t)(k / 8) * (size_t)ddn + (size_t)r) * 8 + (size_t)(k % 8)] =
-                        (uint16_t)h->dn.col[src];
-                    if (h->dn.sgn[src] < 0)
-                        sg[((size_t)(r / 64) * (size_t)std::max(ng8, 1) + (size_t)(k / 8)) * 8 + (size_t)(k % 8)] |=
-                            1ull << (r % 64);
-                }
+                int cp = 0, cn = 0;
+                for (int k = 0; k < h->dn.row_nnz[(size_t)r]; k++)
+                    (h->dn.sgn[(size_t)k * (size_t)ddn + (size_t)r] < 0 ? cn : cp)++;
+                np_col[(size_t)r] = (cp + 7) / 8;
+                nn_col[(size_t)r] = (cn + 3) / 4;
+                npm = std::max(npm, np_col[(size_t)r]);
+                nnm = std::max(nnm, nn_col[(size_t)r]);
             }
-            d.dn_idx16 = upload<uint16_t>(gi.data(), gi.size() * 2, total);
-            d.dn_sgn64 = upload<uint64_t>(sg.data(), sg.size() * 8, total);
+            std::vector<uint16_t> pi((size_t)npm * (size_t)ddn * 8, (uint16_t)ddn);
+            std::vector<uint16_t> ni((size_t)nnm * (size_t)ddn * 4, (uint16_t)ddn);
+            std::vector<uint8_t> pn((size_t)nchunk * 2, 0);
+            for (int64_t r = 0; r < ddn; r++) {
+                int cp = 0, cn = 0;
+                for (int k = 0; k < h->dn.row_nnz[(size_t)r]; k++) {
+                    const size_t src = (size_t)k * (size_t)ddn + (size_t)r;
+                    const uint16_t c = (uint16_t)h->dn.col[src];
+                    if (h->dn.sgn[src] < 0) {
+                        ni[((size_t)(cn / 4) * (size_t)ddn + (size_t)r) * 4 + (size_t)(cn % 4)] = c;
+                        cn++;
+                    } else {
+                        pi[((size_t)(cp / 8) * (size_t)ddn + (size_t)r) * 8 + (size_t)(cp % 8)] = c;
+                        cp++;
+                    }
+                }
+                uint8_t *slot = &pn[(size_t)(r / 64) * 2];
+                slot[0] = (uint8_t)std::max<int>(slot[0], np_col[(size_t)r]);
+                slot[1] = (uint8_t)std::max<int>(slot[1], nn_col[(size_t)r]);
+            }
+            d.dn_pidx = upload<uint16_t>(pi.data(), pi.size() * 2, total);
+            d.dn_nidx = upload<uint16_t>(ni.data(), ni.size() * 2, total);
+            d.dn_pn = upload<uint8_t>(pn.data(), pn.size(), total);
+            d.dn_np = npm;
+            d.dn_nn = nnm;
         }
     }
     upload_blocked_up(h, total);
@@ -340,8 +393,11 @@ static HvArgs hv_args(const hubbard *h)
     a.dn_ngroups = h->dev.dn_ngroups;
     a.dn_groups16 = reinterpret_cast<const uint4 *>(h->dev.dn_groups16);
     a.dn_nq8 = h->dev.dn_nq8;
-    a.dn_idx16 = reinterpret_cast<const uint4 *>(h->dev.dn_idx16);
-    a.dn_sgn64 = h->dev.dn_sgn64;
+    a.dn_pidx = reinterpret_cast<const uint4 *>(h->dev.dn_pidx);
+    a.dn_nidx = reinterpret_cast<const uint2 *>(h->dev.dn_nidx);
+    a.dn_pn = h->dev.dn_pn;
+    a.dn_np = h->dev.dn_np;
+    a.dn_nn = h->dev.dn_nn;
     a.up_blk = h->dev.up_blk;
     a.up_nint = h->dev.up_nint;
     a.up_next = h->dev.up_next;
@@ -350,6 +406,7 @@ static HvArgs hv_args(const hubbard *h)
     a.up_max_block = h->dev.up_max_block;
     a.up_line = h->dev.up_line;
     a.up_line_w = h->dev.up_line_w;
+    a.up_line_ipad = h->dev.up_line_ipad;
     a.up_cnt = h->dev.up_cnt;
     a.dim_up = h->up.dim;
     a.dim_dn = h->dn.dim;

@@ -109,6 +109,28 @@ __device__ inline T class_amp(const T (&a)[4], uint32_t c)
 }
 constexpr uint32_t kGtRowMask = 0x00FFFFFFu;
 
+// The factor an up-spin entry contributes with: +-1 from its sign bit (the
+// high word of +-1.0 built by one and-or), times the class amplitude in the
+// per-bond kernels.  acc = fma(factor, x, acc) rounds exactly as acc +- x.
+__device__ inline uint32_t and_or(uint32_t a, uint32_t smask, uint32_t vor)
+{
+    uint32_t r;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(smask), "v"(vor));
+    return r;
+}
+template <typename T, bool GT>
+__device__ inline T signed_factor(const T (&a)[4], uint32_t e)
+{
+    if (GT)
+        return flip_sign(class_amp(a, (e >> 24) & 3u), e & 0x80000000u);
+    // one instruction: the sign bit of e with the rest of +1.0's (high) word
+    const uint32_t hi = and_or(e, 0x80000000u, sizeof(T) == 8 ? 0x3FF00000u : 0x3F800000u);
+    if constexpr (sizeof(T) == 8)
+        return __hiloint2double((int)hi, 0);
+    else
+        return __int_as_float((int)hi);
+}
+
 // Row pass.  MODE as in the file comment; for HV_RESIDUAL y is the scratch
 // vector z and alpha is the shift.
 template <typename T, int RPB, int MODE, bool G16, bool GT>
@@ -249,26 +271,29 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
 // FP64 row pass (one amplitude; rows of at most 13,312 elements).
 //
 // The same product as hv_rows_kernel with one row per workgroup (an FP64 row
-// of the 4x4 lattice fills the LDS), with fewer instructions per entry: the
-// 16-bit element index becomes the byte address by one shift that reads the
-// half word in place (SDWA), and the entry's sign comes from a 64-bit word
-// shared by the wave (bit l for lane l, one word per entry slot of 64
-// columns, loaded with scalar loads), which picks the high half of +1 or -1
-// for the FMA that adds the gathered value: three instructions per entry
-// instead of about six.  The row sits in a statically sized LDS array, so an
-// address needs no base.  A column's entry groups are loaded one column
-// ahead, and the next row is loaded into registers (16-byte loads) while the
-// current one is gathered and written to LDS after the barrier that ends it.
+// of the 4x4 lattice fills the LDS), with two instructions per entry and no
+// sign handling: a column's hops are split by sign, those of sign + in groups
+// of eight 16-bit element indices and those of sign - in groups of four, and
+// the gathered value is added to, or subtracted from, the sum (the negation
+// is an operand modifier).  The 16-bit index becomes the byte address by one
+// shift that reads the half word in place (SDWA).  Padding entries gather the
+// zero slot after the row.  Each wave takes 64 columns at a time; the group
+// counts of its column chunks sit one per lane of a register and reach the
+// wave by a lane read, so no scalar load waits inside the column loop.  The
+// row sits in a statically sized LDS array, so an address needs no base.  A
+// column's entry groups are loaded one column ahead, and the next row is
+// loaded into registers (16-byte loads) while the current one is gathered
+// and written to LDS after the barrier that ends it.
 constexpr int kRowThreads = 1024;
 
 struct Row64Args {
-    const uint4 *__restrict__ idx;      // [g][d] -> eight 16-bit element indices
-    const uint64_t *__restrict__ sgn;   // [(d / 64) * ng + g][8]
-    const uint8_t *__restrict__ nq;     // groups of eight per 64 columns
+    const uint4 *__restrict__ pidx;     // [g][d] -> eight 16-bit element indices of + hops
+    const uint2 *__restrict__ nidx;     // [g][d] -> four 16-bit element indices of - hops
+    const uint8_t *__restrict__ pn;     // per 64 columns: + groups, - groups (two bytes)
     const uint32_t *__restrict__ states_up;
     const uint32_t *__restrict__ states_dn;
     int64_t dim_up;
-    int dim_dn, ng;
+    int dim_dn;
     double t, U;
 };
 
@@ -288,15 +313,13 @@ __device__ inline uint32_t lds_off_hi(uint32_t e)
         : "v"(e));
     return r;
 }
-// high half of +1.0 or -1.0, chosen by this lane's bit of the wave-uniform mask
-__device__ inline int sign_hi(uint64_t mask, int pos_hi, int neg_hi)
+__device__ inline double lds_at(const double *xs, uint32_t byte)
 {
-    int r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(pos_hi), "v"(neg_hi), "s"(mask));
-    return r;
+    return *reinterpret_cast<const double *>(reinterpret_cast<const unsigned char *>(xs) + byte);
 }
 
-template <int MODE, bool VEC, int CH, int NG>
+// NP groups of eight + hops and NN groups of four - hops at most per column
+template <int MODE, bool VEC, int CH, int NP, int NN>
 __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, const double *__restrict__ x, int64_t ldx,
                                                                 double *__restrict__ y, int64_t ldy, double alpha,
                                                                 double beta, const double *__restrict__ coef)
@@ -311,7 +334,7 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
         beta = coef[2];
         cshift = coef[3];
     }
-    const int ddn = p.dim_dn, tid = (int)threadIdx.x;
+    const int ddn = p.dim_dn, tid = (int)threadIdx.x, lane = tid & 63;
     // staging units: 16-byte pairs (rows 16-byte aligned) or single elements
     typedef typename std::conditional<VEC, double2, double>::type SU;
     const int nu = VEC ? ddn >> 1 : ddn;
@@ -365,19 +388,27 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
     };
 
     const double mt = -p.t, U = p.U;
-    const int pos_hi = 0x3FF00000, neg_hi = (int)0xBFF00000;
-    const uint32_t *__restrict__ nq32 = reinterpret_cast<const uint32_t *>(p.nq);
-    // groups of eight entries of the wave's 64 columns (0 past the row; wave-uniform)
-    auto group_count = [&](int grp) -> int {
-        return grp * 64 < ddn ? (int)((nq32[grp >> 2] >> ((grp & 3) * 8)) & 0xffu) : 0;
+    // lane k holds the group counts of this wave's k-th column chunk (chunk
+    // wave + 16 k); a wave takes at most 64 chunks (rows of up to 65,536 elements)
+    const int wv = tid >> 6, nchunk = (ddn + 63) >> 6;
+    uint32_t cnt_lane = 0;
+    if (wv + 16 * lane < nchunk)
+        cnt_lane = *reinterpret_cast<const uint16_t *>(p.pn + 2 * (wv + 16 * lane));
+    auto counts = [&](int k) -> uint32_t {
+        return wv + 16 * k < nchunk ? (uint32_t)__builtin_amdgcn_readlane((int)cnt_lane, k) : 0u;
     };
     // a column's entry groups (all of them, so one memory round trip per column)
-    auto load_groups = [&](int d, int nq, uint4 (&e)[NG], uint32_t &sd) {
+    auto load_groups = [&](int d, uint32_t c, uint4 (&ep)[NP], uint2 (&en)[NN], uint32_t &sd) {
         const int dd = d < ddn ? d : ddn - 1;
+        const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
 #pragma unroll
-        for (int g = 0; g < NG; g++)
-            if (g < nq)
-                e[g] = p.idx[(size_t)g * (size_t)ddn + (size_t)dd];
+        for (int g = 0; g < NP; g++)
+            if (g < np)
+                ep[g] = p.pidx[(size_t)g * (size_t)ddn + (size_t)dd];
+#pragma unroll
+        for (int g = 0; g < NN; g++)
+            if (g < nn)
+                en[g] = p.nidx[(size_t)g * (size_t)ddn + (size_t)dd];
         sd = p.states_dn[dd];
     };
     int64_t r = blockIdx.x;
@@ -390,43 +421,52 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
         if (r + gridDim.x < p.dim_up)
             load_row(r + gridDim.x);
         const uint32_t su = p.states_up[r];
-        int grp = __builtin_amdgcn_readfirstlane(tid >> 6);
-        int nq = group_count(grp);
-        uint4 e[NG];
+        uint32_t c = counts(0);
+        uint4 ep[NP];
+        uint2 en[NN];
         uint32_t sd = 0;
-        load_groups(tid, nq, e, sd);
-        for (int d0 = 0; d0 < ddn; d0 += kRowThreads) {
+        load_groups(tid, c, ep, en, sd);
+        int k = 0;
+        for (int d0 = 0; d0 < ddn; d0 += kRowThreads, k++) {
             const int d = d0 + tid;
             // the next column's entries load while this one is gathered
-            const int grpn = grp + kRowThreads / 64;
-            const int nqn = group_count(grpn);
-            uint4 en[NG];
+            const uint32_t cn = counts(k + 1);
+            uint4 epn[NP];
+            uint2 enn[NN];
             uint32_t sdn = 0;
             constexpr bool ahead = MODE != HV_FUSED;  // the fused mode has no registers to spare
             if (ahead && d0 + kRowThreads < ddn)
-                load_groups(d + kRowThreads, nqn, en, sdn);
-            if (nq > 0) {
-                const uint64_t *__restrict__ sp = p.sgn + (size_t)grp * (size_t)p.ng * 8;
+                load_groups(d + kRowThreads, cn, epn, enn, sdn);
+            const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
+            {
                 double h0 = 0.0, h1 = 0.0;
 #pragma unroll
-                for (int g = 0; g < NG; g++) {
-                    if (g < nq) {
-                        uint64_t m[8];
-#pragma unroll
-                        for (int u = 0; u < 8; u++)
-                            m[u] = sp[g * 8 + u];
-                        const uint32_t ev[4] = {e[g].x, e[g].y, e[g].z, e[g].w};
+                for (int g = 0; g < NP; g++) {
+                    if (g < np) {
+                        const uint32_t ev[4] = {ep[g].x, ep[g].y, ep[g].z, ep[g].w};
                         double xv[8];
 #pragma unroll
-                        for (int u = 0; u < 8; u++) {
-                            const uint32_t a = (u & 1) ? lds_off_hi(ev[u >> 1]) : lds_off_lo(ev[u >> 1]);
-                            xv[u] = *reinterpret_cast<const double *>(reinterpret_cast<const unsigned char *>(xs) + a);
-                        }
+                        for (int u = 0; u < 8; u++)
+                            xv[u] = lds_at(xs, (u & 1) ? lds_off_hi(ev[u >> 1]) : lds_off_lo(ev[u >> 1]));
 #pragma unroll
                         for (int u = 0; u < 8; u += 2) {
-                            h0 = fma(__hiloint2double(sign_hi(m[u], pos_hi, neg_hi), 0), xv[u], h0);
-                            h1 = fma(__hiloint2double(sign_hi(m[u + 1], pos_hi, neg_hi), 0), xv[u + 1], h1);
+                            h0 += xv[u];
+                            h1 += xv[u + 1];
                         }
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < NN; g++) {
+                    if (g < nn) {
+                        const uint32_t ev[2] = {en[g].x, en[g].y};
+                        double xv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; u++)
+                            xv[u] = lds_at(xs, (u & 1) ? lds_off_hi(ev[u >> 1]) : lds_off_lo(ev[u >> 1]));
+                        h0 -= xv[0];
+                        h1 -= xv[1];
+                        h0 -= xv[2];
+                        h1 -= xv[3];
                     }
                 }
                 if (d < ddn) {
@@ -441,15 +481,17 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                         *yp = hx - alpha * xd;
                 }
             }
-            grp = grpn;
-            nq = nqn;
+            c = cn;
             if (ahead) {
 #pragma unroll
-                for (int g = 0; g < NG; g++)
-                    e[g] = en[g];
+                for (int g = 0; g < NP; g++)
+                    ep[g] = epn[g];
+#pragma unroll
+                for (int g = 0; g < NN; g++)
+                    en[g] = enn[g];
                 sd = sdn;
             } else if (d0 + kRowThreads < ddn) {
-                load_groups(d + kRowThreads, nqn, e, sd);
+                load_groups(d + kRowThreads, cn, ep, en, sd);
             }
         }
         __syncthreads();
@@ -757,7 +799,7 @@ __global__ __launch_bounds__(1024) void hv_blocks_kernel(BlockArgs p, const T *_
 
 struct LineArgs {
     const uint4 *__restrict__ line;    // per row: 32 slots = 8 x uint4
-    const uint32_t *__restrict__ cnt;  // next << 16 | nint
+    const uint32_t *__restrict__ cnt;  // per row: internal, external hops, their maxima over the row's group of eight (bytes 0..3)
     const int32_t *__restrict__ bstart;
     int64_t dim_up, dim_dn;
     int nblocks, nslab;
@@ -772,14 +814,18 @@ struct LineArgs {
 // (internal hops from the front, external from the back): each of the eight
 // lanes of a row group loads its own 16 bytes of it and a hop's entry reaches
 // the other lanes by a permute within the group, so the line costs one load
-// instead of eight.  The next row group's line, hop counts (one word) and
-// running output are loaded one step ahead, which leaves the external rows as
-// the only memory round trip of a step.  Internal hops are summed with the
-// sign applied by flipping the sign bit; -t (and alpha) multiply the sum once.
-// External rows are read four at a time.
+// instead of eight.  The next row group's line, hop counts (one word, which
+// also carries the group's largest counts) and running output are loaded one
+// step ahead, which leaves the external rows as the only memory round trip of
+// a step.  A hop adds its row with one FMA by +-1 (the factor's high word is
+// the entry's sign bit or-ed into that of 1.0); -t (and alpha) multiply the
+// sum once.  External rows are read four at a time, from 32-bit byte offsets
+// where the vector allows (X32).  Padded lines (IPAD) let the internal slots
+// be read without a per-slot test.  Workgroups whose slab lies inside the
+// rows test no bounds; the slab at the rows' ends tests each lane.
 // W = 32: one 128-byte line per row; W = 64 (rows of 33 to 64 hops): two lines,
 // lane q of a row group holding slots 4q..4q+3 of each.
-template <typename T, int MODE, bool GT, int W>
+template <typename T, int MODE, bool GT, int W, bool IPAD, bool X32>
 __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__restrict__ x, int64_t ldx,
                                                         T *__restrict__ y, int64_t ldy, double alpha,
                                                         const double *__restrict__ coef,
@@ -843,155 +889,185 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
         const int64_t d = d0 + q * EPL;
         const bool dok = d < p.dim_dn, whole = d + EPL <= p.dim_dn;
         const int gbase = lane & ~7;
-        // running output of row r (zero past the last column)
-        auto load_prev = [&](int64_t r) -> vec {
-            const T *yp = y + r * ldy + d;
-            if (whole)
-                return __builtin_nontemporal_load(reinterpret_cast<const vec *>(yp));
-            vec v = (vec)(T)0;
-            if (dok) {
+        const unsigned char *__restrict__ xb = reinterpret_cast<const unsigned char *>(x);
+        const uint32_t rowb = (uint32_t)(ldx * (int64_t)sizeof(T)), colb = (uint32_t)(d * (int64_t)sizeof(T));
+        // FULL: the slab lies inside the rows, so every lane's vector is whole
+        // (rows start on 16 bytes) and no access needs a bounds test; the slab
+        // holding the rows' ends tests each lane and never touches padding
+        auto run = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            // running output of row r (zero past the last column)
+            auto load_prev = [&](int64_t r) -> vec {
+                const T *yp = y + r * ldy + d;
+                if (FULL || whole)
+                    return __builtin_nontemporal_load(reinterpret_cast<const vec *>(yp));
+                vec v = (vec)(T)0;
+                if (dok) {
 #pragma unroll
-                for (int e = 0; e < EPL; e++)
-                    v[e] = d + e < p.dim_dn ? yp[e] : (T)0;
-            }
-            return v;
-        };
-        // Lane q of a row group holds slots 4q..4q+3 of the row's line; entry
-        // k reaches every lane of the group by a permute within the group.
-        constexpr int NL = W / 32;  // 128-byte lines per row
-        uint4 Em[NL];
-#pragma unroll
-        for (int h = 0; h < NL; h++)
-            Em[h] = make_uint4(0u, 0u, 0u, 0u);
-        uint32_t C = 0;
-        vec prev = (vec)(T)0;
-        int rb = wave * 8;
-        if (rb < bs) {
-            const int64_t r = b0 + min(rb + sub, bs - 1);
-#pragma unroll
-            for (int h = 0; h < NL; h++)
-                Em[h] = p.line[(r * NL + h) * 8 + q];
-            C = p.cnt[r];
-            if (rb + sub < bs)
-                prev = load_prev(r);
-        }
-        for (; rb < bs; rb += nwave * 8) {
-            const int rl = min(rb + sub, bs - 1);
-            const bool okr = rb + sub < bs;
-            const int64_t r = b0 + rl;
-            T *yp = y + r * ldy + d;
-            // the next row group's entries, counts and running output, a step ahead
-            uint4 En[NL];
+                    for (int e = 0; e < EPL; e++)
+                        v[e] = d + e < p.dim_dn ? yp[e] : (T)0;
+                }
+                return v;
+            };
+            // external row of entry e at this lane's columns: with X32 a 32-bit
+            // byte offset from x (row and row stride below 2^24, the vector below
+            // 4 GB) by one 24-bit multiply-add, which ignores the entry's sign
+            // and class bits
+            auto load_ext = [&](uint32_t e) -> vec {
+                if (FULL && X32)
+                    return *reinterpret_cast<const vec *>(xb + (__umul24(e, rowb) + colb));
+                const T *row = x + (int64_t)(e & (GT ? kGtRowMask : 0x7fffffffu)) * ldx;
+                if (FULL)
+                    return *reinterpret_cast<const vec *>(row + d);
+                return load_row(row, d);
+            };
+            // Lane q of a row group holds slots 4q..4q+3 of the row's line; entry
+            // k reaches every lane of the group by a permute within the group.
+            constexpr int NL = W / 32;  // 128-byte lines per row
+            uint4 Em[NL];
 #pragma unroll
             for (int h = 0; h < NL; h++)
-                En[h] = Em[h];
-            uint32_t Cn = 0;
-            vec prevn = (vec)(T)0;
-            const int rbn = rb + nwave * 8;
-            if (rbn < bs) {
-                const int64_t rn = b0 + min(rbn + sub, bs - 1);
+                Em[h] = make_uint4(0u, 0u, 0u, 0u);
+            uint32_t C = 0;
+            vec prev = (vec)(T)0;
+            int rb = wave * 8;
+            if (rb < bs) {
+                const int64_t r = b0 + min(rb + sub, bs - 1);
 #pragma unroll
                 for (int h = 0; h < NL; h++)
-                    En[h] = p.line[(rn * NL + h) * 8 + q];
-                Cn = p.cnt[rn];
-                if (rbn + sub < bs)
-                    prevn = load_prev(rn);
+                    Em[h] = p.line[(r * NL + h) * 8 + q];
+                C = p.cnt[r];
+                if (rb + sub < bs)
+                    prev = load_prev(r);
             }
-            const int ni = (int)(C & 0xffffu), ne = (int)(C >> 16);
-            int nim = ni, nem = ne;
-            for (int o = 8; o < 64; o <<= 1) {
-                nim = max(nim, __shfl_xor(nim, o, 64));
-                nem = max(nem, __shfl_xor(nem, o, 64));
-            }
-            nim = __builtin_amdgcn_readfirstlane(nim);
-            nem = __builtin_amdgcn_readfirstlane(nem);
-            auto entry = [&](int k) -> uint32_t {
-                const uint4 &E = Em[k >> 5];
-                const uint32_t c = (k & 3) == 0 ? E.x : (k & 3) == 1 ? E.y : (k & 3) == 2 ? E.z : E.w;
-                return (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + ((k & 31) >> 2)) << 2, (int)c);
-            };
-            vec acc = (vec)(T)0;
+            for (; rb < bs; rb += nwave * 8) {
+                const int rl = min(rb + sub, bs - 1);
+                const bool okr = rb + sub < bs;
+                const int64_t r = b0 + rl;
+                T *yp = y + r * ldy + d;
+                // the next row group's entries, counts and running output, a step ahead
+                uint4 En[NL];
 #pragma unroll
-            for (int k0 = 0; k0 < W; k0 += 8) {
-                if (k0 < nim) {
+                for (int h = 0; h < NL; h++)
+                    En[h] = Em[h];
+                uint32_t Cn = 0;
+                vec prevn = (vec)(T)0;
+                const int rbn = rb + nwave * 8;
+                if (rbn < bs) {
+                    const int64_t rn = b0 + min(rbn + sub, bs - 1);
+#pragma unroll
+                    for (int h = 0; h < NL; h++)
+                        En[h] = p.line[(rn * NL + h) * 8 + q];
+                    Cn = p.cnt[rn];
+                    if (rbn + sub < bs)
+                        prevn = load_prev(rn);
+                }
+                const int ni = (int)(C & 0xffu), ne = (int)((C >> 8) & 0xffu);
+                // the largest counts of the eight rows (the same in every lane)
+                const int nim = __builtin_amdgcn_readfirstlane((int)((C >> 16) & 0xffu));
+                const int nem = __builtin_amdgcn_readfirstlane((int)(C >> 24));
+                auto entry = [&](int k) -> uint32_t {
+                    const uint4 &E = Em[k >> 5];
+                    const uint32_t c = (k & 3) == 0 ? E.x : (k & 3) == 1 ? E.y : (k & 3) == 2 ? E.z : E.w;
+                    return (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + ((k & 31) >> 2)) << 2, (int)c);
+                };
+                vec acc = (vec)(T)0;
+                // internal hops, eight slots at a time.  Slot k past the row's
+                // count reads the zero row: with padded lines (IPAD) the line
+                // itself holds it up to the largest count of the group, so
+                // only the group's last, partial chunk selects
+                auto internal = [&](int k0, auto sel_tag) {
+                    constexpr bool SEL = decltype(sel_tag)::value;
+                    const int lim = IPAD ? nim : ni;
                     vec v[8];
                     uint32_t ev[8];
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
                         ev[u] = entry(k0 + u);
-                        const int li = k0 + u < ni ? (int)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) : bs;
+                        const int li =
+                            (!SEL || k0 + u < lim) ? (int)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) : bs;
                         v[u] = xs[li * 8 + q];
                     }
 #pragma unroll
                     for (int u = 0; u < 8; u++) {
-                        const uint32_t sg = ev[u] & 0x80000000u;
-                        const T ac = GT ? class_amp(am, (ev[u] >> 24) & 3u) : (T)1;
+                        const T f = signed_factor<T, GT>(am, ev[u]);
 #pragma unroll
                         for (int c = 0; c < EPL; c++)
-                            acc[c] += GT ? ac * flip_sign(v[u][c], sg) : flip_sign(v[u][c], sg);
+                            acc[c] = fma(f, v[u][c], acc[c]);
+                    }
+                };
+#pragma unroll
+                for (int k0 = 0; k0 < W; k0 += 8) {
+                    if (k0 < nim) {
+                        if (IPAD && k0 + 8 <= nim)
+                            internal(k0, std::false_type{});
+                        else
+                            internal(k0, std::true_type{});
                     }
                 }
-            }
 #pragma unroll
-            for (int k0 = 0; k0 < W; k0 += XB) {
-                if (k0 < nem) {
-                    vec v[XB];
-                    uint32_t ev[XB];
+                for (int k0 = 0; k0 < W; k0 += XB) {
+                    if (k0 < nem) {
+                        vec v[XB];
+                        uint32_t ev[XB];
 #pragma unroll
-                    for (int u = 0; u < XB; u++) {
-                        const bool live = k0 + u < ne;
-                        ev[u] = entry(W - 1 - (k0 + u));
-                        // slots past this row's external count issue no load
-                        v[u] = (vec)(T)0;
-                        if (live)
-                            v[u] = load_row(x + (int64_t)(ev[u] & (GT ? kGtRowMask : 0x7fffffffu)) * ldx, d);
-                    }
+                        for (int u = 0; u < XB; u++) {
+                            ev[u] = entry(W - 1 - (k0 + u));
+                            // slots past this row's external count issue no load
+                            v[u] = (vec)(T)0;
+                            if (k0 + u < ne)
+                                v[u] = load_ext(ev[u]);
+                        }
 #pragma unroll
-                    for (int u = 0; u < XB; u++) {
-                        const bool live = k0 + u < ne;
-                        const uint32_t sg = ev[u] & 0x80000000u;
-                        const T ac = GT ? class_amp(am, (ev[u] >> 24) & 3u) : (T)1;
+                        for (int u = 0; u < XB; u++) {
+                            // and add nothing (factor 0)
+                            const T f = k0 + u < ne ? signed_factor<T, GT>(am, ev[u]) : (T)0;
 #pragma unroll
-                        for (int c = 0; c < EPL; c++)
-                            acc[c] += live ? (GT ? ac * flip_sign(v[u][c], sg) : flip_sign(v[u][c], sg)) : (T)0;
-                    }
-                }
-            }
-            if (okr && dok) {
-                const vec xv = xs[rl * 8 + q];
-                const vec out = prev + scale * acc;  // in the residual mode prev = row pass of H x - alpha x
-#pragma unroll
-                for (int e = 0; e < EPL; e++) {
-                    if (d + e < p.dim_dn) {
-                        if (MODE == HV_LANCZOS) {
-                            acc0 += (double)out[e] * (double)xv[e];
-                        } else if (MODE == HV_FUSED) {
-                            acc0 += (double)out[e] * (double)xv[e];
-                            acc1 += (double)out[e] * (double)out[e];
-                            acc2 += (double)xv[e] * (double)xv[e];
-                        } else if (MODE == HV_RESIDUAL) {
-                            acc0 += (double)out[e] * (double)out[e];
-                            acc1 += (double)xv[e] * ((double)out[e] + alpha * (double)xv[e]);
+                            for (int c = 0; c < EPL; c++)
+                                acc[c] = fma(f, v[u][c], acc[c]);
                         }
                     }
                 }
-                if (MODE != HV_RESIDUAL) {
-                    if (whole) {
-                        __builtin_nontemporal_store(out, reinterpret_cast<vec *>(yp));
-                    } else {
+                if (okr && (FULL || dok)) {
+                    const vec xv = xs[rl * 8 + q];
+                    const vec out = prev + scale * acc;  // in the residual mode prev = row pass of H x - alpha x
 #pragma unroll
-                        for (int e = 0; e < EPL; e++)
-                            if (d + e < p.dim_dn)
-                                yp[e] = out[e];
+                    for (int e = 0; e < EPL; e++) {
+                        if (FULL || d + e < p.dim_dn) {
+                            if (MODE == HV_LANCZOS) {
+                                acc0 += (double)out[e] * (double)xv[e];
+                            } else if (MODE == HV_FUSED) {
+                                acc0 += (double)out[e] * (double)xv[e];
+                                acc1 += (double)out[e] * (double)out[e];
+                                acc2 += (double)xv[e] * (double)xv[e];
+                            } else if (MODE == HV_RESIDUAL) {
+                                acc0 += (double)out[e] * (double)out[e];
+                                acc1 += (double)xv[e] * ((double)out[e] + alpha * (double)xv[e]);
+                            }
+                        }
+                    }
+                    if (MODE != HV_RESIDUAL) {
+                        if (FULL || whole) {
+                            __builtin_nontemporal_store(out, reinterpret_cast<vec *>(yp));
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < EPL; e++)
+                                if (d + e < p.dim_dn)
+                                    yp[e] = out[e];
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int h = 0; h < NL; h++)
-                Em[h] = En[h];
-            C = Cn;
-            prev = prevn;
-        }
+                for (int h = 0; h < NL; h++)
+                    Em[h] = En[h];
+                C = Cn;
+                prev = prevn;
+            }
+        };
+        if (d0 + SL <= p.dim_dn)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
     }
     if (MODE != HV_STORE) {
         // all partial sums of the workgroup in one round: wave sums, one
@@ -1133,53 +1209,67 @@ static void launch_rows_rpb(const RowArgs &ra, bool g16, bool gt, const HvPlan &
 static bool row64_ok(const HvArgs &a, const HvPlan &pl)
 {
     // rows of up to 13 elements per thread are staged through registers
-    return a.tcls == nullptr && a.dn_idx16 != nullptr && a.dn_sgn64 != nullptr && pl.rows_rpb == 1 &&
-           a.w_dn <= 32 && a.dim_dn <= 13 * kRowThreads;
+    return a.tcls == nullptr && a.dn_pidx != nullptr && pl.rows_rpb == 1 && a.w_dn <= 32 &&
+           a.dim_dn <= 13 * kRowThreads;
 }
 
 // The FP64 row pass of hv_rows64_kernel: CH staging units per thread (16-byte
-// pairs when x and y rows start on 16 bytes, else single elements).
-template <int MODE>
-static void launch_rows64_mode(const Row64Args &ra, const HvPlan &pl, const double *x, int64_t ldx, double *y,
-                               int64_t ldy, double alpha, const double *coef, hipStream_t s)
+// pairs when x and y rows start on 16 bytes, else single elements); group
+// slots for the table's largest counts (three groups of + hops and four of -
+// hops cover the square lattices, eight of each any row of up to 32 hops).
+template <int MODE, bool VEC, int CH>
+static void launch_rows64_groups(const Row64Args &ra, int np, int nn, const HvPlan &pl, const double *x, int64_t ldx,
+                                 double *y, int64_t ldy, double alpha, const double *coef, hipStream_t s)
 {
-    const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0) && ldx % 2 == 0 && ldy % 2 == 0;
-    const int64_t units = vec ? ra.dim_dn / 2 : ra.dim_dn;
-    const int need = (int)((units + kRowThreads - 1) / kRowThreads);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(pl.rows_grid), dim3(kRowThreads), 0, s, ra, x, ldx, y, ldy, alpha, 0.0, coef);
         HUB_HIP(hipGetLastError());
     };
+    if (np <= 3 && nn <= 4)
+        go(hv_rows64_kernel<MODE, VEC, CH, 3, 4>);
+    else
+        go(hv_rows64_kernel<MODE, VEC, CH, 4, 8>);
+}
+
+template <int MODE>
+static void launch_rows64_mode(const Row64Args &ra, int np, int nn, const HvPlan &pl, const double *x, int64_t ldx,
+                               double *y, int64_t ldy, double alpha, const double *coef, hipStream_t s)
+{
+    const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0) && ldx % 2 == 0 && ldy % 2 == 0;
+    const int64_t units = vec ? ra.dim_dn / 2 : ra.dim_dn;
+    const int need = (int)((units + kRowThreads - 1) / kRowThreads);
     if (need > (vec ? 7 : 13))
         fail(HUBBARD_EDEVICE, "row too long for the FP64 row pass");
+    if (np > 4 || nn > 8)
+        fail(HUBBARD_EDEVICE, "too many hops per column for the FP64 row pass");
     if (vec)
-        go(hv_rows64_kernel<MODE, true, 7, 4>);
+        launch_rows64_groups<MODE, true, 7>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
     else
-        go(hv_rows64_kernel<MODE, false, 13, 4>);
+        launch_rows64_groups<MODE, false, 13>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
 }
 
 static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, int64_t ldx, double *y, int64_t ldy,
                           int mode, double alpha, const double *coef, hipStream_t s)
 {
     Row64Args ra;
-    ra.idx = a.dn_idx16;
-    ra.sgn = a.dn_sgn64;
-    ra.nq = a.dn_nq8;
+    ra.pidx = a.dn_pidx;
+    ra.nidx = a.dn_nidx;
+    ra.pn = a.dn_pn;
     ra.states_up = a.states_up;
     ra.states_dn = a.states_dn;
     ra.dim_up = a.dim_up;
     ra.dim_dn = (int)a.dim_dn;
-    ra.ng = (a.w_dn + 7) / 8 > 0 ? (a.w_dn + 7) / 8 : 1;
     ra.t = a.t;
     ra.U = a.U;
+    const int np = a.dn_np, nn = a.dn_nn;
     if (mode == HV_STORE)
-        launch_rows64_mode<HV_STORE>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+        launch_rows64_mode<HV_STORE>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
     else if (mode == HV_LANCZOS)
-        launch_rows64_mode<HV_LANCZOS>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+        launch_rows64_mode<HV_LANCZOS>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
     else if (mode == HV_FUSED)
-        launch_rows64_mode<HV_FUSED>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+        launch_rows64_mode<HV_FUSED>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
     else
-        launch_rows64_mode<HV_RESIDUAL>(ra, pl, x, ldx, y, ldy, alpha, coef, s);
+        launch_rows64_mode<HV_RESIDUAL>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
 }
 
 template <typename T>
@@ -1270,18 +1360,32 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                                    ldyr, alpha, coef, partials);
                 HUB_HIP(hipGetLastError());
             };
+            // 32-bit external offsets: rows and row stride below 2^24, x below 4 GB
+            const int64_t rowb = ldx * (int64_t)sizeof(T);
+            const bool x32 = a.dim_up < (1 << 24) && rowb < (1 << 24) && a.dim_up * rowb < ((int64_t)1 << 32);
+            const bool ipad = a.up_line_ipad != 0;
+            auto pick = [&](auto mode_tag) {
+                constexpr int M = decltype(mode_tag)::value;
+                if (gt)
+                    w64 ? gol(hv_lines_kernel<T, M, true, 64, false, false>)
+                        : gol(hv_lines_kernel<T, M, true, 32, false, false>);
+                else if (!w64)
+                    (ipad && x32) ? gol(hv_lines_kernel<T, M, false, 32, true, true>)
+                                  : gol(hv_lines_kernel<T, M, false, 32, false, false>);
+                else if (x32)
+                    ipad ? gol(hv_lines_kernel<T, M, false, 64, true, true>)
+                         : gol(hv_lines_kernel<T, M, false, 64, false, true>);
+                else
+                    gol(hv_lines_kernel<T, M, false, 64, false, false>);
+            };
             if (mode == HV_STORE)
-                w64 ? (gt ? gol(hv_lines_kernel<T, HV_STORE, true, 64>) : gol(hv_lines_kernel<T, HV_STORE, false, 64>))
-                    : (gt ? gol(hv_lines_kernel<T, HV_STORE, true, 32>) : gol(hv_lines_kernel<T, HV_STORE, false, 32>));
+                pick(std::integral_constant<int, HV_STORE>{});
             else if (mode == HV_LANCZOS)
-                w64 ? (gt ? gol(hv_lines_kernel<T, HV_LANCZOS, true, 64>) : gol(hv_lines_kernel<T, HV_LANCZOS, false, 64>))
-                    : (gt ? gol(hv_lines_kernel<T, HV_LANCZOS, true, 32>) : gol(hv_lines_kernel<T, HV_LANCZOS, false, 32>));
+                pick(std::integral_constant<int, HV_LANCZOS>{});
             else if (mode == HV_FUSED)
-                w64 ? (gt ? gol(hv_lines_kernel<T, HV_FUSED, true, 64>) : gol(hv_lines_kernel<T, HV_FUSED, false, 64>))
-                    : (gt ? gol(hv_lines_kernel<T, HV_FUSED, true, 32>) : gol(hv_lines_kernel<T, HV_FUSED, false, 32>));
+                pick(std::integral_constant<int, HV_FUSED>{});
             else
-                w64 ? (gt ? gol(hv_lines_kernel<T, HV_RESIDUAL, true, 64>) : gol(hv_lines_kernel<T, HV_RESIDUAL, false, 64>))
-                    : (gt ? gol(hv_lines_kernel<T, HV_RESIDUAL, true, 32>) : gol(hv_lines_kernel<T, HV_RESIDUAL, false, 32>));
+                pick(std::integral_constant<int, HV_RESIDUAL>{});
             return pl.blk_grid;
         }
         if (mode == HV_STORE)

@@ -66,12 +66,14 @@ struct DeviceTables {
     // groups of eight 16-bit entries (element index | sign<<15)
     uint16_t *dn_groups16 = nullptr;
     uint8_t *dn_nq8 = nullptr;     // groups of eight needed by the 64 columns of a wave
-    // FP64 row pass (one amplitude, rows of at most kRow64Max elements): the
-    // same groups of eight holding the element index alone (padding: the zero
-    // slot at index dim_dn), and the signs apart, one 64-bit word per group
-    // of 64 columns and entry slot (bit l: the entry of column 64 g + l is -)
-    uint16_t *dn_idx16 = nullptr;
-    uint64_t *dn_sgn64 = nullptr;
+    // FP64 row pass (one amplitude, rows of at most kRow64Max elements): per
+    // column the hops of sign + in groups of eight 16-bit element indices and
+    // those of sign - in groups of four, each in ascending column order
+    // (padding: the zero slot at index dim_dn), and per 64 columns the two
+    // group counts (one byte each); dn_np, dn_nn: the largest counts
+    uint16_t *dn_pidx = nullptr, *dn_nidx = nullptr;
+    uint8_t *dn_pn = nullptr;
+    int dn_np = 0, dn_nn = 0;
     // up table for the blocked slab pass: rows are grouped in blocks of equal
     // occupation of the top sites; per row the hops that stay in the block come
     // first (block-local row | sign<<31), then the others (row | sign<<31)
@@ -79,13 +81,18 @@ struct DeviceTables {
     uint16_t *up_nint = nullptr, *up_next = nullptr;
     int32_t *up_bstart = nullptr;  // nblocks + 1 row offsets
     int up_nblocks = 0, up_max_block = 0;
-    // the same entries with one 32-slot line per row (rows of at most 32
-    // hops): internal hops from the front, external from the back; the two
-    // counts packed as next << 16 | nint
+    // the same entries with one 32-slot line per row (two, 64 slots, for rows
+    // of 33 to 64 hops, or where 32 slots leave no room for the padding):
+    // internal hops from the front, external from the back; per row one word
+    // with the internal and external counts and their largest values over the
+    // row's group of eight (bytes 0..3).  Padded lines (up_line_ipad): the
+    // slots past a row's internal count, up to the largest count of its group,
+    // hold the block's zero row
     uint32_t *up_line = nullptr, *up_cnt = nullptr;
     size_t bytes = 0;
     double *tcls = nullptr;  // amplitude of each class (per-bond amplitudes only)
     int up_line_w = 32;      // slots per row of up_line (32 or 64)
+    int up_line_ipad = 0;
 };
 
 }  // namespace hub
@@ -132,6 +139,7 @@ struct HvArgs {
     int ncls = 0;
     double amp4[4] = {0.0, 0.0, 0.0, 0.0};  // the classes, for the two-pass kernels (ncls <= kTwoPassClasses)
     int up_line_w = 32;  // slots per row of up_line: 32 (one 128-byte line) or 64 (two)
+    int up_line_ipad = 0;  // internal slots padded with the zero row up to the group's largest count
     const uint32_t *states_up, *states_dn, *up_rows, *dn_cols;
     const uint16_t *nnz_up, *nnz_dn;
     const uint4 *dn_groups64, *dn_groups32;
@@ -139,8 +147,10 @@ struct HvArgs {
     int dn_ngroups;
     const uint4 *dn_groups16;  // null when rows exceed 32767 elements
     const uint8_t *dn_nq8;
-    const uint4 *dn_idx16 = nullptr;      // FP64 row-pass indices (null: not built)
-    const uint64_t *dn_sgn64 = nullptr;   // their signs, per 64 columns and slot
+    const uint4 *dn_pidx = nullptr;       // FP64 row pass: + hops, eight per group (null: not built)
+    const uint2 *dn_nidx = nullptr;       // - hops, four per group
+    const uint8_t *dn_pn = nullptr;       // group counts per 64 columns
+    int dn_np = 0, dn_nn = 0;             // their largest values
     const uint32_t *up_blk;
     const uint16_t *up_nint, *up_next;
     const int32_t *up_bstart;

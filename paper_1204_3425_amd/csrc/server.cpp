@@ -40,11 +40,12 @@ struct Job {
 // Upper bound of the device bytes a request needs: the two work vectors on
 // padded rows, partial sums, the batched engine's coefficient history, and the
 // tables with at most n_edges entries per row: up side (row-major entries,
-// blocked entries, the entry lines: one 128-byte line per row when a row has
-// at most 32 hops, two when it has at most 64, none beyond; counts, states)
+// blocked entries, the entry lines: up to two 128-byte lines per row when a
+// row has at most 64 hops (one when 32 slots hold the row and its padding),
+// none beyond; counts, states)
 // and down side (column-major entries, 64- and 32-bit offset groups, 16-bit
-// groups, counts, states, and the FP64 row pass's 16-bit indices and sign
-// words).
+// groups, counts, states, and the FP64 row pass's 16-bit indices split by
+// sign: at most w/8 groups of eight + hops and w/4 groups of four - hops).
 size_t footprint(const hubbard_request &r)
 {
     const uint64_t du = binomial(r.sites, r.n_up), dd = binomial(r.sites, r.n_dn);
@@ -52,10 +53,10 @@ size_t footprint(const hubbard_request &r)
     const size_t ld = (size_t)((dd + 63) / 64 * 64);
     const size_t vecs = 2 * es * (size_t)du * ld + 64 * 1024 + 16 * (size_t)std::max(1, r.max_iter);
     const size_t w = (size_t)std::max(1, r.n_edges);
-    const size_t lines = w <= 32 ? 128 : (w <= 64 ? 256 : 0);
+    const size_t lines = w <= 64 ? 256 : 0;  // one or two 128-byte lines
     const size_t up = (size_t)du * (8 * w + 14 + lines);
-    const size_t g8 = (w + 7) / 8;  // groups of eight entries per column
-    const size_t dn = (size_t)dd * (14 * w + 56 + 16 * g8 + g8);
+    const size_t g8 = (w + 7) / 8, g4 = (w + 3) / 4;  // groups of eight or four entries per column
+    const size_t dn = (size_t)dd * (14 * w + 56 + 16 * g8 + 16 * g8 + 8 * g4 + 1);
     return vecs + up + dn;
 }
 
