@@ -164,7 +164,14 @@ int hubbard_set_seed(hubbard_h h, uint64_t seed);
  * interaction from rows staged in LDS, then the up-spin hops as row
  * combinations).  x, y: device arrays of dim elements in J order, double under
  * HUBBARD_FP64 and float under HUBBARD_MIXED; y is overwritten and must not
- * overlap x.  Asynchronous on the handle's stream. */
+ * overlap x.  Asynchronous on the handle's stream.  When the rows of x or y do
+ * not start on 128 bytes (dim_dn not a multiple of 16 doubles or 32 floats)
+ * and the up-spin rows have at most 64 hops, the product routes through two work vectors at the stride ld_pref that the
+ * handle allocates on the first such call (2 * dim_up * ld_pref elements of the
+ * current precision, kept until hubbard_free; ENOMEM if they do not fit): the
+ * row pass writes its result and a copy of x there, and the up-spin pass reads
+ * them and writes y.  Calls share these vectors: a call on another stream
+ * waits for the previous one. */
 int hubbard_apply(hubbard_h h, const void *x, void *y);
 
 /* y = H x as hubbard_apply, with x and y stored as dim_up rows of dim_dn
@@ -173,8 +180,9 @@ int hubbard_apply(hubbard_h h, const void *x, void *y);
  * hubbard_info gives the stride the library uses for its own vectors
  * (ld_pref, a multiple of 64 elements): strides that are a multiple of 128
  * bytes (and buffers aligned to 128 bytes) select the blocked up-spin pass,
- * which works on one cache line of every row at a time; other strides take a
- * slower pass.  Where the one-pass kernel runs (rows too wide for LDS, or a
+ * which works on one cache line of every row at a time; other strides route
+ * through the handle's work vectors as in hubbard_apply (up-spin rows of more
+ * than 64 hops take a slower pass instead).  Where the one-pass kernel runs (rows too wide for LDS, or a
  * handle with more than four distinct per-bond amplitudes) ld_pref is dim_dn
  * and only dense rows (ldx = ldy = dim_dn) are accepted: other strides return
  * EINVAL. */

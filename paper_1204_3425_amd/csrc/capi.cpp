@@ -102,6 +102,15 @@ struct PinnedBuf {
 
 static void free_device(hubbard *h)
 {
+    if (h->apply_work) {
+        (void)hipFree(h->apply_work);
+        h->apply_work = nullptr;
+        h->apply_work_bytes = 0;
+    }
+    if (h->apply_ev) {
+        (void)hipEventDestroy(h->apply_ev);
+        h->apply_ev = nullptr;
+    }
     DeviceTables &d = h->dev;
     void *ptrs[] = {d.states_up, d.states_dn, d.up_rows, d.dn_cols, d.nnz_up, d.nnz_dn,
                     d.dn_groups64, d.dn_groups32, d.dn_nq, d.dn_groups16, d.dn_nq8, d.dn_pidx, d.dn_nidx, d.dn_pn, d.up_blk, d.up_nint, d.up_next,
@@ -493,7 +502,8 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
 
     // one allocation for both work vectors; after the replay it is reused as
     // the FP64 scratch of the residual (2 * npad * sizeof(T) >= npad * 8 bytes)
-    DevBuf work(2 * sizeof(T) * (size_t)npad);
+    // with psi requested it also holds the FP64 residual's two padded vectors
+    DevBuf work(std::max(2 * sizeof(T), o.psi ? (size_t)16 : (size_t)0) * (size_t)npad);
     T *vecs[2] = {work.as<T>(), work.as<T>() + npad};
     const int nd = dfl.nd;
     const int db = defl_blocks(h->up.dim);
@@ -758,8 +768,10 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
         c = -c;
     launch_scale(o.psi, c, n, s);
     // FP64 residual |H psi - E0 psi| and Rayleigh quotient <psi|H|psi>
+    // rows of psi are dense: the row pass copies them to padded rows beside
+    // its result, for the up-spin pass
     const int hb64 = launch_hv2<double>(args, plan64, o.psi, h->dn.dim, nullptr, 0, work.as<double>(), ld, HV_RESIDUAL,
-                                        out.e0, nullptr, partials.as<double>(), s);
+                                        out.e0, nullptr, partials.as<double>(), s, work.as<double>() + npad);
     launch_reduce(partials.as<double>(), hb64, hb64, 2, S + 4, s);
     HUB_HIP(hipMemcpyAsync(hh, S + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HUB_HIP(hipStreamSynchronize(s));
@@ -1171,19 +1183,43 @@ static int apply_impl(hubbard_h h, const void *x, int64_t ldx, void *y, int64_t 
         fail(HUBBARD_EINVAL, "x and y overlap");
     use_device(h);
     const HvArgs a = hv_args(h);
-    if (h->precision == HUBBARD_FP64) {
-        const HvPlan pl = make_hv_plan(a, 8);
-        if (!pl.two_pass && (ldx != ddn || ldy != ddn))
-            fail(HUBBARD_EINVAL, "rows too wide for the staged kernels: only dense rows (ld = dim_dn) are supported");
-        launch_hv2<double>(a, pl, static_cast<const double *>(x), ldx, static_cast<double *>(y), ldy, nullptr, 0,
-                           HV_STORE, 0.0, nullptr, nullptr, h->stream);
-    } else {
-        const HvPlan pl = make_hv_plan(a, 4);
-        if (!pl.two_pass && (ldx != ddn || ldy != ddn))
-            fail(HUBBARD_EINVAL, "rows too wide for the staged kernels: only dense rows (ld = dim_dn) are supported");
-        launch_hv2<float>(a, pl, static_cast<const float *>(x), ldx, static_cast<float *>(y), ldy, nullptr, 0,
-                          HV_STORE, 0.0, nullptr, nullptr, h->stream);
+    const HvPlan pl = make_hv_plan(a, (int)es);
+    if (!pl.two_pass && (ldx != ddn || ldy != ddn))
+        fail(HUBBARD_EINVAL, "rows too wide for the staged kernels: only dense rows (ld = dim_dn) are supported");
+    // rows not on 128 bytes: the H.v routes through two padded work vectors
+    // (the row pass writes them, the up-spin pass reads them and writes y)
+    const int64_t slw = 128 / (int64_t)es;
+    void *wx = nullptr, *wy = nullptr;
+    if (pl.two_pass && pl.blk_grid > 0 && a.up_line && (ldx % slw != 0 || ldy % slw != 0)) {
+        const size_t npad = (size_t)h->up.dim * (size_t)pl.ld;
+        const size_t need = 2 * npad * es;
+        if (h->apply_work_bytes < need) {
+            if (h->apply_work) {
+                HUB_HIP(hipStreamSynchronize(h->stream));
+                HUB_HIP(hipFree(h->apply_work));
+                h->apply_work = nullptr;
+                h->apply_work_bytes = 0;
+            }
+            HUB_HIP(hipMalloc(&h->apply_work, need));
+            h->apply_work_bytes = need;
+        }
+        if (!h->apply_ev)
+            HUB_HIP(hipEventCreateWithFlags(&h->apply_ev, hipEventDisableTiming));
+        else
+            HUB_HIP(hipStreamWaitEvent(h->stream, h->apply_ev, 0));
+        wx = h->apply_work;
+        wy = static_cast<char *>(h->apply_work) + npad * es;
     }
+    if (h->precision == HUBBARD_FP64)
+        launch_hv2<double>(a, pl, static_cast<const double *>(x), ldx, static_cast<double *>(y), ldy, nullptr, 0,
+                           HV_STORE, 0.0, nullptr, nullptr, h->stream, static_cast<double *>(wx),
+                           static_cast<double *>(wy));
+    else
+        launch_hv2<float>(a, pl, static_cast<const float *>(x), ldx, static_cast<float *>(y), ldy, nullptr, 0,
+                          HV_STORE, 0.0, nullptr, nullptr, h->stream, static_cast<float *>(wx),
+                          static_cast<float *>(wy));
+    if (wx)
+        HUB_HIP(hipEventRecord(h->apply_ev, h->stream));
     return HUBBARD_OK;
 }
 

@@ -95,6 +95,8 @@ struct RowArgs {
     int ngroups;
     double t, U;
     double amp[4];  // per-bond amplitude classes (GT kernels)
+    void *xc;       // null, or rows at stride ldc that receive a copy of each staged row
+    int64_t ldc;
 };
 
 // Per-bond amplitudes (GT kernels): entries carry a class of at most four
@@ -186,6 +188,8 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                             const_cast<T *>(x)[(r0 + q) * ldx + d] = val;
                         }
                         xs[q * slot + d] = val;
+                        if (p.xc)
+                            static_cast<T *>(p.xc)[(r0 + q) * p.ldc + d] = val;
                     }
                 }
             }
@@ -295,6 +299,8 @@ struct Row64Args {
     int64_t dim_up;
     int dim_dn;
     double t, U;
+    double *xc;  // null, or rows at stride ldc that receive a copy of each staged row
+    int64_t ldc;
 };
 
 __device__ inline uint32_t lds_off_lo(uint32_t e)
@@ -362,6 +368,7 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
     auto store_row = [&](int64_t r) {
         SU *xs2 = reinterpret_cast<SU *>(xs);
         SU *xw = reinterpret_cast<SU *>(const_cast<double *>(x) + r * ldx);
+        SU *xc = reinterpret_cast<SU *>(p.xc + r * p.ldc);
 #pragma unroll
         for (int u = 0; u < CH; u++) {
             const int i = u * kRowThreads + tid;
@@ -371,6 +378,8 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                     // the q - a_j f_j update of the previous step, formed here and kept
                     val = val - cshift * w[u];
                     xw[i] = val;
+                } else if (p.xc) {
+                    xc[i] = val;
                 }
                 xs2[i] = val;
             }
@@ -380,6 +389,8 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
             if (MODE == HV_FUSED) {
                 val = val - cshift * wt;
                 const_cast<double *>(x)[r * ldx + ddn - 1] = val;
+            } else if (p.xc) {
+                p.xc[r * p.ldc + ddn - 1] = val;
             }
             xs[ddn - 1] = val;
         }
@@ -806,6 +817,9 @@ struct LineArgs {
     int contig;  // rows not on 128 bytes: each XCD takes a contiguous range of slabs
     double t;
     double amp[4];
+    void *yo;      // where the result goes (y itself, or rows at stride ldyo)
+    int64_t ldyo;
+    int yoal;      // alignment of the result rows: 16 or 8 bytes (vector stores), else 0
 };
 
 // Blocked slab pass, line layout (rows of at most 64 hops).  Same workgroup
@@ -944,7 +958,7 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                 const int rl = min(rb + sub, bs - 1);
                 const bool okr = rb + sub < bs;
                 const int64_t r = b0 + rl;
-                T *yp = y + r * ldy + d;
+                T *yp = static_cast<T *>(p.yo) + r * p.ldyo + d;
                 // the next row group's entries, counts and running output, a step ahead
                 uint4 En[NL];
 #pragma unroll
@@ -1047,9 +1061,21 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                         }
                     }
                     if (MODE != HV_RESIDUAL) {
-                        if (FULL || whole) {
+                        bool done = false;
+                        if ((FULL || whole) && p.yoal == 16) {
                             __builtin_nontemporal_store(out, reinterpret_cast<vec *>(yp));
-                        } else {
+                            done = true;
+                        }
+                        if constexpr (EPL == 4) {
+                            if (!done && (FULL || whole) && p.yoal == 8) {
+                                // float rows on 8 bytes: two 8-byte stores
+                                typedef __attribute__((ext_vector_type(2))) T vec2;
+                                __builtin_nontemporal_store(vec2{out[0], out[1]}, reinterpret_cast<vec2 *>(yp));
+                                __builtin_nontemporal_store(vec2{out[2], out[3]}, reinterpret_cast<vec2 *>(yp + 2));
+                                done = true;
+                            }
+                        }
+                        if (!done) {
 #pragma unroll
                             for (int e = 0; e < EPL; e++)
                                 if (d + e < p.dim_dn)
@@ -1249,9 +1275,11 @@ static void launch_rows64_mode(const Row64Args &ra, int np, int nn, const HvPlan
 }
 
 static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, int64_t ldx, double *y, int64_t ldy,
-                          int mode, double alpha, const double *coef, hipStream_t s)
+                          int mode, double alpha, const double *coef, hipStream_t s, double *xc, int64_t ldc)
 {
     Row64Args ra;
+    ra.xc = xc;
+    ra.ldc = ldc;
     ra.pidx = a.dn_pidx;
     ra.nidx = a.dn_nidx;
     ra.pn = a.dn_pn;
@@ -1274,7 +1302,8 @@ static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, in
 
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
-               int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s)
+               int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s, T *xpad,
+               T *ypad)
 {
     if (!pl.two_pass) {
         // rows too wide for LDS: the one-pass kernel (dense rows only)
@@ -1299,10 +1328,26 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     ra.t = a.t;
     ra.U = a.U;
     T *yr = mode == HV_RESIDUAL ? scratch : y;
-    const int64_t ldyr = mode == HV_RESIDUAL ? lds_ : ldy;
+    int64_t ldyr = mode == HV_RESIDUAL ? lds_ : ldy;
+    T *yo = y;  // where the up-spin pass writes the result
+    int64_t ldyo = ldy;
+    // Rows not on 128 bytes (a caller's dense vector) with padded work rows
+    // given: the row pass writes its result to the padded rows and copies each
+    // staged row of x beside it, so the up-spin pass runs on cache-line slabs
+    // and writes the sum straight to y.
+    const int64_t slw = 128 / (int64_t)sizeof(T), v16 = 16 / (int64_t)sizeof(T);
+    const bool dense = ldx % slw != 0 || ldyr % slw != 0;
+    const bool repad = pl.blk_grid > 0 && a.up_line && dense && xpad &&
+                       (mode == HV_STORE ? ypad != nullptr : mode == HV_RESIDUAL);
+    ra.xc = repad ? xpad : nullptr;
+    ra.ldc = pl.ld;
+    if (repad && mode == HV_STORE) {
+        yr = ypad;
+        ldyr = pl.ld;
+    }
     if (sizeof(T) == 8 && row64_ok(a, pl))
         launch_rows64(a, pl, reinterpret_cast<const double *>(x), ldx, reinterpret_cast<double *>(yr), ldyr, mode,
-                      alpha, coef, s);
+                      alpha, coef, s, reinterpret_cast<double *>(ra.xc), ra.ldc);
     else if (pl.rows_rpb == 3)
         launch_rows_rpb<T, 3>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else if (pl.rows_rpb == 2)
@@ -1310,11 +1355,14 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     else
         launch_rows_rpb<T, 1>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
 
+    if (repad) {
+        x = xpad;
+        ldx = pl.ld;
+    }
     // the blocked passes load 16 bytes per lane: rows must start on 16 bytes
     // (on 128 bytes each row segment is one cache line)
-    const int64_t slw = 128 / (int64_t)sizeof(T), v16 = 16 / (int64_t)sizeof(T);
     const bool on16 = ldx % v16 == 0 && ldyr % v16 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)yr % 16 == 0;
-    const int contig = (ldx % slw != 0 || ldyr % slw != 0) ? 1 : 0;
+    const int contig = (ldx % slw != 0 || ldyr % slw != 0 || (mode != HV_RESIDUAL && ldyo % slw != 0)) ? 1 : 0;
     if (pl.blk_grid > 0 && on16) {
         BlockArgs ba;
         ba.ent = a.up_blk;
@@ -1349,6 +1397,11 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             la.nslab = pl.blk_nslab;
             la.contig = contig;
             la.t = a.t;
+            la.yo = yo;
+            la.ldyo = ldyo;
+            la.yoal = ((uintptr_t)yo % 16 == 0 && ldyo % v16 == 0)                         ? 16
+                      : ((uintptr_t)yo % 8 == 0 && (ldyo * (int64_t)sizeof(T)) % 8 == 0) ? 8
+                                                                                         : 0;
             const bool w64 = a.up_line_w == 64;
             for (int c = 0; c < 4; c++)
                 la.amp[c] = a.amp4[c];
@@ -1430,8 +1483,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
 }
 
 template int launch_hv2<double>(const HvArgs &, const HvPlan &, const double *, int64_t, double *, int64_t, double *,
-                                int64_t, int, double, const double *, double *, hipStream_t);
+                                int64_t, int, double, const double *, double *, hipStream_t, double *, double *);
 template int launch_hv2<float>(const HvArgs &, const HvPlan &, const float *, int64_t, float *, int64_t, float *,
-                               int64_t, int, double, const double *, double *, hipStream_t);
+                               int64_t, int, double, const double *, double *, hipStream_t, float *, float *);
 
 }  // namespace hub

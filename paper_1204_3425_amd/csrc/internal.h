@@ -112,6 +112,12 @@ struct hubbard {
     uint64_t seed = 12043425ull;
     // device bytes a solve with psi may hold for its resident Lanczos basis
     size_t basis_limit = SIZE_MAX;
+    // padded work rows for hubbard_apply on rows not on 128 bytes (two vectors
+    // at the library's row stride, allocated on first use), and the event of
+    // their last use, so that a call on another stream waits for it
+    void *apply_work = nullptr;
+    size_t apply_work_bytes = 0;
+    hipEvent_t apply_ev = nullptr;
 };
 
 namespace hub {
@@ -200,9 +206,14 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes);
 // (lds_); scratch (the row-pass output) is used by HV_RESIDUAL only, where y
 // is not written.  Partial sums: pl.nparts values (HV_RESIDUAL: twice that).
 // Returns the number of partial sums written (HV_RESIDUAL: twice that many values).
+// xpad, ypad: null, or dim_up x pl.ld work arrays.  When the rows of x or y do
+// not start on 128 bytes, HV_STORE with both (HV_RESIDUAL with xpad) routes
+// through them: the row pass writes its result to ypad (scratch) and a copy
+// of x to xpad, and the up-spin pass runs on those and writes y.
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
-               int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s);
+               int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s,
+               T *xpad = nullptr, T *ypad = nullptr);
 
 template <typename T>
 void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);
