@@ -508,7 +508,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     const int nd = dfl.nd;
     const int db = defl_blocks(h->up.dim);
     DevBuf partials(sizeof(double) *
-                    (size_t)(std::max(3 * std::max(std::max(hb, plan64.nparts), sb), nd * db) + 64));
+                    (size_t)(std::max((3 + 2 * kFusedDefl) * std::max(std::max(hb, plan64.nparts), sb), nd * db) + 64));
     DevBuf scal(sizeof(double) * (8 + kMaxDeflate + 1) + sizeof(double) * 2 * (size_t)(max_iter + 1));
     double *S = scal.as<double>();
     double *D = S + 8;  // projections psi_l . q of the deflated step
@@ -559,16 +559,37 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     // b_{j+1} comes from the expanded norm (the reduction's RED_FUSED mode).
     // Small sectors, where a breakdown or an exhausted space is near, keep the
     // update pass and the norm of the stored vector.
-    const bool fused = nd == 0 && plan.two_pass && plan.blk_grid > 0 && n >= kFusedMinDim;
+    // With up to kFusedDefl lower states (one amplitude, line layout) the
+    // deflated step is fused too: the up-spin pass also sums psi_l.q and
+    // psi_l.f_j, the reduction forms g_l = psi_l.(q - a_j f_j) and takes
+    // sum_l g_l^2 off the expanded norm, and the next row pass subtracts
+    // sum_l g_l psi_l while it forms f_{j+1} (so P is applied to q - a_j f_j
+    // as in the unfused step, with no pass of its own).
+    const bool fused_defl = nd >= 1 && nd <= kFusedDefl && !args.tcls && args.up_line;
+    const bool fused = (nd == 0 || fused_defl) && plan.two_pass && plan.blk_grid > 0 && n >= kFusedMinDim;
+    HvDefl hdefl;
+    hdefl.psi = dfl.psi;
+    hdefl.nd = nd;
+    hdefl.pdim = n;
+    hdefl.g = S + 8;
     auto hv_step = [&](T *C, T *P) {
+        if (fused && nd > 0)
+            return launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, HV_FUSED_DEFL, 0.0, S, partials.as<double>(),
+                                 s, nullptr, nullptr, &hdefl);
         return launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, fused ? HV_FUSED : HV_LANCZOS, 0.0,
                              fused ? S : S + 1, partials.as<double>(), s);
     };
     auto finish_step = [&](T *C, T *P, int np, int j0) {
         if (fused) {
-            launch_reduce_step(partials.as<double>(), np, RED_FUSED, S, hist, j0, s);
+            launch_reduce_step(partials.as<double>(), np, RED_FUSED, S, hist, j0, s, nd);
             // steps whose expanded norm lost its digits form X_{j+1} and its
             // norm explicitly; both launches return at once otherwise
+            if (nd > 0) {
+                const int nb = launch_fused_fix_defl<T>(P, C, S, dfl.psi, nd, n, h->up.dim, h->dn.dim, ld,
+                                                        partials.as<double>(), s);
+                launch_reduce_step(partials.as<double>(), nb, RED_FIX, S, hist, j0, s);
+                return;
+            }
             launch_fused_fix<T>(P, C, S, npad, partials.as<double>(), sb, s);
             launch_reduce_step(partials.as<double>(), sb, RED_FIX, S, hist, j0, s);
             return;

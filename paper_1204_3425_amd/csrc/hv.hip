@@ -97,6 +97,7 @@ struct RowArgs {
     double amp[4];  // per-bond amplitude classes (GT kernels)
     void *xc;       // null, or rows at stride ldc that receive a copy of each staged row
     int64_t ldc;
+    HvDefl defl;    // HV_FUSED_DEFL
 };
 
 // Per-bond amplitudes (GT kernels): entries carry a class of at most four
@@ -142,28 +143,34 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
+    constexpr bool FUSED = MODE == HV_FUSED || MODE == HV_FUSED_DEFL;
     double cshift = 0.0;
     if (MODE == HV_LANCZOS) {
         alpha = coef[0];
         beta = coef[1];
-    } else if (MODE == HV_FUSED) {
+    } else if (FUSED) {
         alpha = coef[1];
         beta = coef[2];
         cshift = coef[3];
     }
+    double gd[kFusedDefl] = {};
+    if (MODE == HV_FUSED_DEFL)
+        for (int l = 0; l < p.defl.nd; l++)
+            gd[l] = p.defl.g[l];
     const int64_t ddn = p.dim_dn;
     const int64_t slot = ddn + 1;  // staged row length including the zero slot
     const T mt = GT ? (T)(-1) : (T)(-p.t), U = (T)p.U, a_s = (T)alpha, b_s = (T)beta, c_s = (T)cshift;
     const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     // staging: each thread loads CH elements of each of the RPB rows before it
     // writes any of them to LDS, so a row costs one or two memory round trips
-    constexpr int CH = (MODE == HV_FUSED ? 8 : 16) / RPB;
+    constexpr int CH = (FUSED ? 8 : 16) / RPB;
     const int ddn32 = (int)ddn, nth = (int)blockDim.x;
 
     for (int64_t r0 = (int64_t)blockIdx.x * RPB; r0 < p.dim_up; r0 += (int64_t)gridDim.x * RPB) {
         const int nr = (int)min((int64_t)RPB, p.dim_up - r0);
         for (int d0 = 0; d0 < ddn32; d0 += CH * nth) {
             T v[RPB][CH], w[RPB][CH];
+            double pg[RPB][CH];  // sum_l g_l psi_l (deflated step)
 #pragma unroll
             for (int q = 0; q < RPB; q++) {
 #pragma unroll
@@ -171,8 +178,12 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                     const int d = d0 + u * nth + (int)threadIdx.x;
                     const bool ok = q < nr && d < ddn32;
                     v[q][u] = ok ? x[(r0 + q) * ldx + d] : (T)0;
-                    if (MODE == HV_FUSED)
+                    if (FUSED)
                         w[q][u] = ok ? y[(r0 + q) * ldy + d] : (T)0;
+                    pg[q][u] = 0.0;
+                    if (MODE == HV_FUSED_DEFL && ok)
+                        for (int l = 0; l < p.defl.nd; l++)
+                            pg[q][u] += gd[l] * p.defl.psi[(int64_t)l * p.defl.pdim + (r0 + q) * ddn + d];
                 }
             }
 #pragma unroll
@@ -182,9 +193,12 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                     const int d = d0 + u * nth + (int)threadIdx.x;
                     if (q < nr && d < ddn32) {
                         T val = v[q][u];
-                        if (MODE == HV_FUSED) {
-                            // the q - a_j f_j update of the previous step, formed here and kept
+                        if (FUSED) {
+                            // the q - a_j f_j update of the previous step (projected
+                            // in the deflated step, rounded once), formed here and kept
                             val = val - c_s * w[q][u];
+                            if (MODE == HV_FUSED_DEFL)
+                                val = (T)((double)val - pg[q][u]);
                             const_cast<T *>(x)[(r0 + q) * ldx + d] = val;
                         }
                         xs[q * slot + d] = val;
@@ -260,7 +274,7 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                         T *yp = y + (r0 + q) * ldy + d;
                         if (MODE == HV_STORE)
                             *yp = hx;
-                        else if (MODE == HV_LANCZOS || MODE == HV_FUSED)
+                        else if (MODE == HV_LANCZOS || FUSED)
                             *yp = a_s * hx + b_s * *yp;
                         else
                             *yp = hx - a_s * xv;
@@ -301,6 +315,7 @@ struct Row64Args {
     double t, U;
     double *xc;  // null, or rows at stride ldc that receive a copy of each staged row
     int64_t ldc;
+    HvDefl defl;  // HV_FUSED_DEFL
 };
 
 __device__ inline uint32_t lds_off_lo(uint32_t e)
@@ -331,15 +346,20 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                                                                 double beta, const double *__restrict__ coef)
 {
     __shared__ __align__(16) double xs[kRow64Max + 2];
+    constexpr bool FUSED = MODE == HV_FUSED || MODE == HV_FUSED_DEFL;
     double cshift = 0.0;
     if (MODE == HV_LANCZOS) {
         alpha = coef[0];
         beta = coef[1];
-    } else if (MODE == HV_FUSED) {
+    } else if (FUSED) {
         alpha = coef[1];
         beta = coef[2];
         cshift = coef[3];
     }
+    double gd[kFusedDefl] = {};
+    if (MODE == HV_FUSED_DEFL)
+        for (int l = 0; l < p.defl.nd; l++)
+            gd[l] = p.defl.g[l];
     const int ddn = p.dim_dn, tid = (int)threadIdx.x, lane = tid & 63;
     // staging units: 16-byte pairs (rows 16-byte aligned) or single elements
     typedef typename std::conditional<VEC, double2, double>::type SU;
@@ -355,28 +375,58 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
             const int i = u * kRowThreads + tid;
             if (i < nu) {
                 v[u] = src[i];
-                if (MODE == HV_FUSED)
+                if (FUSED)
                     w[u] = ysrc[i];
             }
         }
         if (tail) {
             vt = x[r * ldx + ddn - 1];
-            if (MODE == HV_FUSED)
+            if (FUSED)
                 wt = y[r * ldy + ddn - 1];
         }
+    };
+    // psi_l at element e of row r (dense rows)
+    auto psi_at = [&](int l, int64_t r, int e) -> double {
+        return p.defl.psi[(int64_t)l * p.defl.pdim + r * (int64_t)ddn + e];
     };
     auto store_row = [&](int64_t r) {
         SU *xs2 = reinterpret_cast<SU *>(xs);
         SU *xw = reinterpret_cast<SU *>(const_cast<double *>(x) + r * ldx);
         SU *xc = reinterpret_cast<SU *>(p.xc + r * p.ldc);
+        // the projection of the deflated step: sum_l g_l psi_l at this
+        // thread's elements (all loads issued before the first use)
+        SU pg[CH];
+        double pgt = 0.0;
+        if (MODE == HV_FUSED_DEFL) {
+#pragma unroll
+            for (int u = 0; u < CH; u++)
+                pg[u] = SU{};
+            for (int l = 0; l < p.defl.nd; l++) {
+#pragma unroll
+                for (int u = 0; u < CH; u++) {
+                    const int i = u * kRowThreads + tid;
+                    if (i < nu) {
+                        if constexpr (VEC)
+                            pg[u] = pg[u] + gd[l] * SU{psi_at(l, r, 2 * i), psi_at(l, r, 2 * i + 1)};
+                        else
+                            pg[u] = pg[u] + gd[l] * psi_at(l, r, i);
+                    }
+                }
+                if (tail)
+                    pgt += gd[l] * psi_at(l, r, ddn - 1);
+            }
+        }
 #pragma unroll
         for (int u = 0; u < CH; u++) {
             const int i = u * kRowThreads + tid;
             if (i < nu) {
                 SU val = v[u];
-                if (MODE == HV_FUSED) {
-                    // the q - a_j f_j update of the previous step, formed here and kept
+                if (FUSED) {
+                    // the q - a_j f_j update of the previous step (projected in
+                    // the deflated step), formed here and kept
                     val = val - cshift * w[u];
+                    if (MODE == HV_FUSED_DEFL)
+                        val = val - pg[u];
                     xw[i] = val;
                 } else if (p.xc) {
                     xc[i] = val;
@@ -386,8 +436,10 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
         }
         if (tail) {
             double val = vt;
-            if (MODE == HV_FUSED) {
+            if (FUSED) {
                 val = val - cshift * wt;
+                if (MODE == HV_FUSED_DEFL)
+                    val = val - pgt;
                 const_cast<double *>(x)[r * ldx + ddn - 1] = val;
             } else if (p.xc) {
                 p.xc[r * p.ldc + ddn - 1] = val;
@@ -445,7 +497,7 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
             uint4 epn[NP];
             uint2 enn[NN];
             uint32_t sdn = 0;
-            constexpr bool ahead = MODE != HV_FUSED;  // the fused mode has no registers to spare
+            constexpr bool ahead = !FUSED;  // the fused modes have no registers to spare
             if (ahead && d0 + kRowThreads < ddn)
                 load_groups(d + kRowThreads, cn, epn, enn, sdn);
             const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
@@ -486,7 +538,7 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                     double *yp = y + r * ldy + d;
                     if (MODE == HV_STORE)
                         *yp = hx;
-                    else if (MODE == HV_LANCZOS || MODE == HV_FUSED)
+                    else if (MODE == HV_LANCZOS || FUSED)
                         *yp = alpha * hx + beta * *yp;
                     else
                         *yp = hx - alpha * xd;
@@ -820,6 +872,7 @@ struct LineArgs {
     void *yo;      // where the result goes (y itself, or rows at stride ldyo)
     int64_t ldyo;
     int yoal;      // alignment of the result rows: 16 or 8 bytes (vector stores), else 0
+    HvDefl defl;   // HV_FUSED_DEFL: the lower vectors psi_l . y and psi_l . x are summed against
 };
 
 // Blocked slab pass, line layout (rows of at most 64 hops).  Same workgroup
@@ -860,13 +913,17 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
             v[e] = d + e < p.dim_dn ? row[d + e] : (T)0;
         return v;
     };
+    constexpr bool FUSED = MODE == HV_FUSED || MODE == HV_FUSED_DEFL;
+    constexpr int ND = MODE == HV_FUSED_DEFL ? kFusedDefl : 0;  // slots for lower vectors
     if (MODE == HV_LANCZOS)
         alpha = coef[0];
-    else if (MODE == HV_FUSED)
+    else if (FUSED)
         alpha = coef[1];
     // y += scale * sum_k (+-x_k): -t, times alpha in the Lanczos modes
     const double mt = GT ? -1.0 : -p.t;
-    const T scale = (MODE == HV_LANCZOS || MODE == HV_FUSED) ? (T)(alpha * mt) : (T)mt;
+    const T scale = (MODE == HV_LANCZOS || FUSED) ? (T)(alpha * mt) : (T)mt;
+    // deflated step: shares of psi_l . y (du) and psi_l . x (dx)
+    double du[ND > 0 ? ND : 1] = {}, dx[ND > 0 ? ND : 1] = {};
     const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwave = blockDim.x >> 6;
@@ -959,27 +1016,40 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                 const bool okr = rb + sub < bs;
                 const int64_t r = b0 + rl;
                 T *yp = static_cast<T *>(p.yo) + r * p.ldyo + d;
-                // the next row group's entries, counts and running output, a step ahead
-                uint4 En[NL];
+                // the lower vectors at this row's elements, loaded while the hops
+                // are summed; the loads are unconditional (clamped in-bounds
+                // indices, unused values weighted 0), so that waiting for them
+                // never waits for the loads issued for the next row group
+                double pv[ND > 0 ? ND : 1][EPL];
+                if (ND > 0) {
 #pragma unroll
-                for (int h = 0; h < NL; h++)
-                    En[h] = Em[h];
-                uint32_t Cn = 0;
-                vec prevn = (vec)(T)0;
-                const int rbn = rb + nwave * 8;
-                if (rbn < bs) {
-                    const int64_t rn = b0 + min(rbn + sub, bs - 1);
+                    for (int l = 0; l < ND; l++) {
+                        const int lc = l < p.defl.nd ? l : 0;
+                        const double *pr = p.defl.psi + (int64_t)lc * p.defl.pdim + r * p.dim_dn;
 #pragma unroll
-                    for (int h = 0; h < NL; h++)
-                        En[h] = p.line[(rn * NL + h) * 8 + q];
-                    Cn = p.cnt[rn];
-                    if (rbn + sub < bs)
-                        prevn = load_prev(rn);
+                        for (int e = 0; e < EPL; e++) {
+                            const bool use = l < p.defl.nd && okr && (FULL || d + e < p.dim_dn);
+                            const int64_t de = (FULL || d + e < p.dim_dn) ? d + e : p.dim_dn - 1;
+                            pv[l][e] = pr[de] * (use ? 1.0 : 0.0);
+                        }
+                    }
                 }
                 const int ni = (int)(C & 0xffu), ne = (int)((C >> 8) & 0xffu);
                 // the largest counts of the eight rows (the same in every lane)
                 const int nim = __builtin_amdgcn_readfirstlane((int)((C >> 16) & 0xffu));
                 const int nem = __builtin_amdgcn_readfirstlane((int)(C >> 24));
+                // the next row group's entries, counts and running output, a
+                // step ahead.  The loads are unconditional (past the block they
+                // read its last row, unused), so the wait counters stay exact
+                // and using this step's data never waits for them.
+                uint4 En[NL];
+                const int rbn = rb + nwave * 8;
+                const int64_t rn = b0 + min(rbn + sub, bs - 1);
+#pragma unroll
+                for (int h = 0; h < NL; h++)
+                    En[h] = p.line[(rn * NL + h) * 8 + q];
+                const uint32_t Cn = p.cnt[rn];
+                const vec prevn = load_prev(rn);
                 auto entry = [&](int k) -> uint32_t {
                     const uint4 &E = Em[k >> 5];
                     const uint32_t c = (k & 3) == 0 ? E.x : (k & 3) == 1 ? E.y : (k & 3) == 2 ? E.z : E.w;
@@ -1050,10 +1120,15 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
                         if (FULL || d + e < p.dim_dn) {
                             if (MODE == HV_LANCZOS) {
                                 acc0 += (double)out[e] * (double)xv[e];
-                            } else if (MODE == HV_FUSED) {
+                            } else if (FUSED) {
                                 acc0 += (double)out[e] * (double)xv[e];
                                 acc1 += (double)out[e] * (double)out[e];
                                 acc2 += (double)xv[e] * (double)xv[e];
+#pragma unroll
+                                for (int l = 0; l < ND; l++) {
+                                    du[l] += pv[l][e] * (double)out[e];
+                                    dx[l] += pv[l][e] * (double)xv[e];
+                                }
                             } else if (MODE == HV_RESIDUAL) {
                                 acc0 += (double)out[e] * (double)out[e];
                                 acc1 += (double)xv[e] * ((double)out[e] + alpha * (double)xv[e]);
@@ -1098,28 +1173,39 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
     if (MODE != HV_STORE) {
         // all partial sums of the workgroup in one round: wave sums, one
         // barrier, then lane 0 of wave 0 adds the waves in a fixed order
-        __shared__ double red[3][16];
-        const double s0 = wave_sum(acc0);
-        const double s1 = (MODE == HV_RESIDUAL || MODE == HV_FUSED) ? wave_sum(acc1) : 0.0;
-        const double s2 = MODE == HV_FUSED ? wave_sum(acc2) : 0.0;
-        if (lane == 0) {
-            red[0][wave] = s0;
-            red[1][wave] = s1;
-            red[2][wave] = s2;
+        constexpr int NS = 3 + 2 * ND;
+        __shared__ double red[NS][16];
+        double sv[NS];
+        sv[0] = wave_sum(acc0);
+        sv[1] = (MODE == HV_RESIDUAL || FUSED) ? wave_sum(acc1) : 0.0;
+        sv[2] = FUSED ? wave_sum(acc2) : 0.0;
+#pragma unroll
+        for (int l = 0; l < ND; l++) {
+            sv[3 + 2 * l] = wave_sum(du[l]);
+            sv[4 + 2 * l] = wave_sum(dx[l]);
         }
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < NS; k++)
+                red[k][wave] = sv[k];
         __syncthreads();
         if (threadIdx.x == 0) {
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-            for (int w = 0; w < nwave; w++) {
-                t0 += red[0][w];
-                t1 += red[1][w];
-                t2 += red[2][w];
-            }
-            partials[blockIdx.x] = t0;
-            if (MODE == HV_RESIDUAL || MODE == HV_FUSED)
-                partials[gridDim.x + blockIdx.x] = t1;
-            if (MODE == HV_FUSED)
-                partials[2 * gridDim.x + blockIdx.x] = t2;
+            double t[NS];
+#pragma unroll
+            for (int k = 0; k < NS; k++)
+                t[k] = 0.0;
+            for (int w = 0; w < nwave; w++)
+#pragma unroll
+                for (int k = 0; k < NS; k++)
+                    t[k] += red[k][w];
+            partials[blockIdx.x] = t[0];
+            if (MODE == HV_RESIDUAL || FUSED)
+                partials[gridDim.x + blockIdx.x] = t[1];
+            if (FUSED)
+                partials[2 * gridDim.x + blockIdx.x] = t[2];
+            // the deflated step's sums for the lower vectors it has
+            for (int k = 3; k < 3 + 2 * p.defl.nd && k < NS; k++)
+                partials[(int64_t)k * gridDim.x + blockIdx.x] = t[k];
         }
     }
 }
@@ -1216,6 +1302,8 @@ static void launch_rows_rpb(const RowArgs &ra, bool g16, bool gt, const HvPlan &
             go(hv_rows_kernel<T, RPB, HV_LANCZOS, true, false>);
         else if (mode == HV_FUSED)
             go(hv_rows_kernel<T, RPB, HV_FUSED, true, false>);
+        else if (mode == HV_FUSED_DEFL)
+            go(hv_rows_kernel<T, RPB, HV_FUSED_DEFL, true, false>);
         else
             go(hv_rows_kernel<T, RPB, HV_RESIDUAL, true, false>);
     } else {
@@ -1225,6 +1313,8 @@ static void launch_rows_rpb(const RowArgs &ra, bool g16, bool gt, const HvPlan &
             go(hv_rows_kernel<T, RPB, HV_LANCZOS, false, false>);
         else if (mode == HV_FUSED)
             go(hv_rows_kernel<T, RPB, HV_FUSED, false, false>);
+        else if (mode == HV_FUSED_DEFL)
+            go(hv_rows_kernel<T, RPB, HV_FUSED_DEFL, false, false>);
         else
             go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false, false>);
     }
@@ -1275,11 +1365,13 @@ static void launch_rows64_mode(const Row64Args &ra, int np, int nn, const HvPlan
 }
 
 static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, int64_t ldx, double *y, int64_t ldy,
-                          int mode, double alpha, const double *coef, hipStream_t s, double *xc, int64_t ldc)
+                          int mode, double alpha, const double *coef, hipStream_t s, double *xc, int64_t ldc,
+                          const HvDefl &defl)
 {
     Row64Args ra;
     ra.xc = xc;
     ra.ldc = ldc;
+    ra.defl = defl;
     ra.pidx = a.dn_pidx;
     ra.nidx = a.dn_nidx;
     ra.pn = a.dn_pn;
@@ -1296,6 +1388,8 @@ static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, in
         launch_rows64_mode<HV_LANCZOS>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
     else if (mode == HV_FUSED)
         launch_rows64_mode<HV_FUSED>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
+    else if (mode == HV_FUSED_DEFL)
+        launch_rows64_mode<HV_FUSED_DEFL>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
     else
         launch_rows64_mode<HV_RESIDUAL>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
 }
@@ -1303,7 +1397,7 @@ static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, in
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s, T *xpad,
-               T *ypad)
+               T *ypad, const HvDefl *defl)
 {
     if (!pl.two_pass) {
         // rows too wide for LDS: the one-pass kernel (dense rows only)
@@ -1341,13 +1435,17 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                        (mode == HV_STORE ? ypad != nullptr : mode == HV_RESIDUAL);
     ra.xc = repad ? xpad : nullptr;
     ra.ldc = pl.ld;
+    const HvDefl dfl = defl ? *defl : HvDefl();
+    if (mode == HV_FUSED_DEFL && (gt || !a.up_line || !(dfl.nd >= 1 && dfl.nd <= kFusedDefl) || !dfl.psi || !dfl.g))
+        fail(HUBBARD_EDEVICE, "fused deflated step: unsupported plan or deflation data");
+    ra.defl = dfl;
     if (repad && mode == HV_STORE) {
         yr = ypad;
         ldyr = pl.ld;
     }
     if (sizeof(T) == 8 && row64_ok(a, pl))
         launch_rows64(a, pl, reinterpret_cast<const double *>(x), ldx, reinterpret_cast<double *>(yr), ldyr, mode,
-                      alpha, coef, s, reinterpret_cast<double *>(ra.xc), ra.ldc);
+                      alpha, coef, s, reinterpret_cast<double *>(ra.xc), ra.ldc, dfl);
     else if (pl.rows_rpb == 3)
         launch_rows_rpb<T, 3>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
     else if (pl.rows_rpb == 2)
@@ -1399,6 +1497,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             la.t = a.t;
             la.yo = yo;
             la.ldyo = ldyo;
+            la.defl = dfl;
             la.yoal = ((uintptr_t)yo % 16 == 0 && ldyo % v16 == 0)                         ? 16
                       : ((uintptr_t)yo % 8 == 0 && (ldyo * (int64_t)sizeof(T)) % 8 == 0) ? 8
                                                                                          : 0;
@@ -1419,7 +1518,15 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             const bool ipad = a.up_line_ipad != 0;
             auto pick = [&](auto mode_tag) {
                 constexpr int M = decltype(mode_tag)::value;
-                if (gt)
+                if constexpr (M == HV_FUSED_DEFL) {
+                    // one amplitude only (checked above)
+                    if (!w64)
+                        (ipad && x32) ? gol(hv_lines_kernel<T, M, false, 32, true, true>)
+                                      : gol(hv_lines_kernel<T, M, false, 32, false, false>);
+                    else
+                        (ipad && x32) ? gol(hv_lines_kernel<T, M, false, 64, true, true>)
+                                      : gol(hv_lines_kernel<T, M, false, 64, false, false>);
+                } else if (gt)
                     w64 ? gol(hv_lines_kernel<T, M, true, 64, false, false>)
                         : gol(hv_lines_kernel<T, M, true, 32, false, false>);
                 else if (!w64)
@@ -1437,6 +1544,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                 pick(std::integral_constant<int, HV_LANCZOS>{});
             else if (mode == HV_FUSED)
                 pick(std::integral_constant<int, HV_FUSED>{});
+            else if (mode == HV_FUSED_DEFL)
+                pick(std::integral_constant<int, HV_FUSED_DEFL>{});
             else
                 pick(std::integral_constant<int, HV_RESIDUAL>{});
             return pl.blk_grid;
@@ -1451,7 +1560,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             gt ? gob(hv_blocks_kernel<T, HV_RESIDUAL, true>) : gob(hv_blocks_kernel<T, HV_RESIDUAL, false>);
         return pl.blk_grid;
     }
-    if (mode == HV_FUSED)
+    if (mode == HV_FUSED || mode == HV_FUSED_DEFL)
         fail(HUBBARD_EDEVICE, "fused Lanczos step needs rows aligned to 16 bytes");
 
     SlabArgs sa;
@@ -1483,8 +1592,10 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
 }
 
 template int launch_hv2<double>(const HvArgs &, const HvPlan &, const double *, int64_t, double *, int64_t, double *,
-                                int64_t, int, double, const double *, double *, hipStream_t, double *, double *);
+                                int64_t, int, double, const double *, double *, hipStream_t, double *, double *,
+                                const HvDefl *);
 template int launch_hv2<float>(const HvArgs &, const HvPlan &, const float *, int64_t, float *, int64_t, float *,
-                               int64_t, int, double, const double *, double *, hipStream_t, float *, float *);
+                               int64_t, int, double, const double *, double *, hipStream_t, float *, float *,
+                               const HvDefl *);
 
 }  // namespace hub

@@ -180,8 +180,18 @@ struct HvPlan {
     size_t blk_lds = 0;
     int nparts = 1;         // largest number of partial sums any launch writes
 };
-enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2, HV_FUSED = 3 };
+enum HvMode { HV_STORE = 0, HV_LANCZOS = 1, HV_RESIDUAL = 2, HV_FUSED = 3, HV_FUSED_DEFL = 4 };
 enum RedMode { RED_PLAIN = 0, RED_DOT = 1, RED_NORM = 2, RED_FUSED = 3, RED_START = 4, RED_FIX = 5 };
+// Lower states a fused deflated step projects out (more take the unfused step).
+constexpr int kFusedDefl = 2;
+// Deflation data of HV_FUSED_DEFL: nd FP64 vectors in dense J order (vector l
+// at psi + l * pdim) and their coefficients g (device, nd values).
+struct HvDefl {
+    const double *psi = nullptr;
+    int nd = 0;
+    int64_t pdim = 0;
+    const double *g = nullptr;
+};
 // Fused Lanczos step: below this ratio b_{j+1}^2 / |q|^2 the expanded norm
 // has lost too many digits and the step is finished by the explicit fix-up
 // (device scalars S[kFixFlag], S[kFixScale]).
@@ -196,6 +206,9 @@ constexpr int kFixFlag = 6, kFixScale = 7;
 // HV_FUSED:    (two-pass plans, padded rows) x <- x - c y is formed and written
 //              back first, then y = alpha H x + beta y; coef = S (S[1] alpha,
 //              S[2] beta, S[3] c); partials [3][n] = shares of y.x, y.y, x.x
+// HV_FUSED_DEFL: as HV_FUSED with x <- x - c y - sum_l g_l psi_l (HvDefl,
+//              nd <= kFusedDefl, line layout of the up-spin entries);
+//              partials [3 + 2l][n] = shares of psi_l.y, [4 + 2l][n] of psi_l.x
 template <typename T>
 void launch_hv(const HvArgs &a, const T *x, T *y, int mode, double alpha, const double *coef, double *partials,
                int nblocks, hipStream_t s);
@@ -213,13 +226,18 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes);
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s,
-               T *xpad = nullptr, T *ypad = nullptr);
+               T *xpad = nullptr, T *ypad = nullptr, const HvDefl *defl = nullptr);
 
 template <typename T>
 void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);
 // the fix-up of a flagged fused step (a no-op when S[kFixFlag] is clear)
 template <typename T>
 void launch_fused_fix(T *w, const T *v, const double *S, int64_t n, double *partials, int nblocks, hipStream_t s);
+// the same for a fused deflated step: w <- w - S[3] v - sum_l S[8 + l] psi_l,
+// rows at stride ld (returns the number of partial sums)
+template <typename T>
+int launch_fused_fix_defl(T *w, const T *v, const double *S, const double *psi, int nd, int64_t pdim, int64_t dim_up,
+                          int64_t dim_dn, int64_t ld, double *partials, hipStream_t s);
 void launch_start_raw(uint64_t seed, double *f, int64_t n, hipStream_t s);
 void launch_start_norm2(const double *given, uint64_t seed, int64_t n, double *partials, int nblocks, hipStream_t s);
 // out[r*ld + d] = (T)(c f[r*dim_dn + d]) and 0 in the row padding; zero (if
@@ -277,7 +295,9 @@ int launch_defl_dots(T *q, const T *v, const double *coef, const double *psi, in
 template <typename T>
 int launch_defl_update(T *q, const double *psi, const double *D, int nd, int64_t dim, int64_t dim_up, int64_t dim_dn,
                        int64_t ld, double *partials, hipStream_t s);
-void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s);
+// nd: lower vectors of a fused deflated step (RED_FUSED)
+void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s,
+                        int nd = 0);
 void launch_init_scalars(double *S, hipStream_t s);
 int stream_blocks(int64_t n);
 

@@ -333,6 +333,55 @@ void launch_fused_fix(T *w, const T *v, const double *S, int64_t n, double *part
 template void launch_fused_fix<double>(double *, const double *, const double *, int64_t, double *, int, hipStream_t);
 template void launch_fused_fix<float>(float *, const float *, const double *, int64_t, double *, int, hipStream_t);
 
+// The same fix-up for a fused deflated step: w <- w - S[3] v - sum_l S[8 + l]
+// psi_l (in FP64, rounded once), rows of w and v at stride ld, psi dense;
+// partial sums of the new vector's squared norm.
+template <typename T>
+__global__ __launch_bounds__(256) void fused_fix_defl_kernel(T *__restrict__ w, const T *__restrict__ v,
+                                                             const double *__restrict__ S,
+                                                             const double *__restrict__ psi, int nd, int64_t pdim,
+                                                             int64_t dim_up, int64_t dim_dn, int64_t ld,
+                                                             double *__restrict__ partials)
+{
+    if (S[kFixFlag] == 0.0)
+        return;
+    __shared__ double red[4];
+    const double cs = S[3];
+    double g[kMaxDeflate];
+    for (int l = 0; l < nd; l++)
+        g[l] = S[8 + l];
+    double acc = 0.0;
+    const int64_t n = dim_up * dim_dn;
+    GRID_STRIDE(i, n)
+    {
+        const int64_t r = i / dim_dn, d = i - r * dim_dn;
+        double x = (double)(w[r * ld + d] - (T)cs * v[r * ld + d]);
+        for (int l = 0; l < nd; l++)
+            x -= g[l] * psi[(int64_t)l * pdim + i];
+        const T q = (T)x;
+        w[r * ld + d] = q;
+        acc += (double)q * (double)q;
+    }
+    double s = block_sum(acc, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = s;
+}
+
+template <typename T>
+int launch_fused_fix_defl(T *w, const T *v, const double *S, const double *psi, int nd, int64_t pdim, int64_t dim_up,
+                          int64_t dim_dn, int64_t ld, double *partials, hipStream_t s)
+{
+    const int nb = stream_blocks(dim_up * dim_dn);
+    hipLaunchKernelGGL(fused_fix_defl_kernel<T>, dim3(nb), dim3(256), 0, s, w, v, S, psi, nd, pdim, dim_up, dim_dn, ld,
+                       partials);
+    HUB_HIP(hipGetLastError());
+    return nb;
+}
+template int launch_fused_fix_defl<double>(double *, const double *, const double *, const double *, int, int64_t,
+                                           int64_t, int64_t, int64_t, double *, hipStream_t);
+template int launch_fused_fix_defl<float>(float *, const float *, const double *, const double *, int, int64_t,
+                                          int64_t, int64_t, int64_t, double *, hipStream_t);
+
 // SplitMix64 (Steele, Lea & Flood 2014): output k of the stream started at
 // `seed` is the published finaliser applied to seed + k * 0x9E3779B97F4A7C15.
 __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k)
@@ -646,10 +695,15 @@ void launch_scale(double *v, double c, int64_t n, hipStream_t s)
 //   that cancel against |y|: when it falls below kFixRatio |y|^2 the step is
 //   flagged (S[kFixFlag] = 1, the old 1/s kept in S[kFixScale]) and b_{j+1}
 //   is left to RED_FIX.
+//   A fused deflated step (stride = nd lower vectors, partials [3 + 2l][n] =
+//   shares of psi_l.y and [4 + 2l][n] of psi_l.x) projects the next vector,
+//   X_{j+1} = y - c X_j - sum_l g_l psi_l with g_l = psi_l.y - c psi_l.x
+//   (S[8 + l]), and subtracts sum_l g_l^2 from the expanded norm.
 // mode RED_FIX (after fused_fix_kernel, only when the step was flagged):
-//   b_{j+1} = |X_{j+1}| from the explicit vector; c = 0, so the next step's
-//   row pass keeps X_{j+1} as it is; the flag is cleared.
-// S = device scalars {1/s of the current vector, alpha, beta, c, -, -, flag, 1/s kept}.
+//   b_{j+1} = |X_{j+1}| from the explicit vector; c = 0 and g = 0, so the
+//   next step's row pass keeps X_{j+1} as it is; the flag is cleared.
+// S = device scalars {1/s of the current vector, alpha, beta, c, -, -, flag,
+// 1/s kept, g_0 .. g_{nd-1}}; RED_START also clears g.
 __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__ partials, int n, int stride,
                                                       double *__restrict__ out, int mode, double *__restrict__ S,
                                                       double *__restrict__ hist, int j)
@@ -670,10 +724,26 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
         }
         const double qq = block_sum(acc1, red);
         const double xx = block_sum(acc2, red);
+        const int nd = stride;  // lower vectors of a deflated step
+        double pu[kMaxDeflate], px[kMaxDeflate];
+        for (int l = 0; l < nd && l < kMaxDeflate; l++) {
+            double au = 0.0, ax = 0.0;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                au += src[(3 + 2 * l) * n + i];
+                ax += src[(4 + 2 * l) * n + i];
+            }
+            pu[l] = block_sum(au, red);
+            px[l] = block_sum(ax, red);
+        }
         if (threadIdx.x == 0) {
             const double a = s * S[0];
             const double c = a * S[0];
-            const double b2 = qq - 2.0 * c * s + c * c * xx;
+            double b2 = qq - 2.0 * c * s + c * c * xx;
+            for (int l = 0; l < nd && l < kMaxDeflate; l++) {
+                const double g = pu[l] - c * px[l];
+                S[8 + l] = g;
+                b2 -= g * g;
+            }
             hist[2 * j] = a;
             S[3] = c;
             if (b2 >= kFixRatio * qq) {
@@ -698,6 +768,8 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
             S[0] = b > 0.0 ? 1.0 / b : 0.0;
             S[1] = S[0];
             S[3] = 0.0;
+            for (int l = 0; l < kMaxDeflate; l++)
+                S[8 + l] = 0.0;
             S[kFixFlag] = 0.0;
         }
         return;
@@ -715,6 +787,8 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
             S[1] = S[0];
             S[2] = 0.0;
             S[3] = 0.0;
+            for (int l = 0; l < kMaxDeflate; l++)
+                S[8 + l] = 0.0;
         } else {
             const double b = sqrt(s);
             hist[2 * j + 1] = b;
@@ -732,9 +806,11 @@ void launch_reduce(const double *partials, int n, int stride, int count, double 
     HUB_HIP(hipGetLastError());
 }
 
-void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s)
+void launch_reduce_step(const double *partials, int n, int mode, double *S, double *hist, int j, hipStream_t s,
+                        int nd)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, partials, n, 0, (double *)nullptr, mode, S, hist, j);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, partials, n, nd, (double *)nullptr, mode, S, hist,
+                       j);
     HUB_HIP(hipGetLastError());
 }
 

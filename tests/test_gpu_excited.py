@@ -174,3 +174,53 @@ def test_lowest_states_large_sector_properties():
         hv = m.apply_rows(Psi[i], rows)
         assert np.all(np.abs(hv - E[i] * Psi[i][rows]) <= res[i]["residual"] + 1e-12)
         assert res[i]["rayleigh"] == pytest.approx(E[i], rel=1e-10)
+
+
+def _free_spectrum(levels, nu, nd):
+    """U = 0: every eigenvalue is a sum over N_up distinct single-particle
+    levels plus a sum over N_dn distinct levels (Slater determinants)."""
+    import itertools
+    su = [sum(c) for c in itertools.combinations(levels, nu)]
+    sd = [sum(c) for c in itertools.combinations(levels, nd)]
+    return np.sort(np.add.outer(su, sd).ravel())
+
+
+FUSED_CASES = [
+    # open chains at U = 0 above the fused-step size (65,536 states), with
+    # non-degenerate lowest levels; k = 4 runs states 1 and 2 through the fused
+    # deflated step and state 3 through the unfused one
+    # rows of 220 elements: the staged row pass
+    ("chain12_4u3d_free", 12, 4, 3, 4),
+    # rows of 12,870 elements: the FP64 one-row pass
+    ("chain16_1u8d_free", 16, 1, 8, 3),
+]
+
+
+@pytest.mark.parametrize("name,ns,nu,nd,k", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_lowest_states_fused_deflation_free_fermions(name, ns, nu, nd, k):
+    """The fused deflated step (the projection of q - a_j f_j folded into the
+    next row pass, the dots with the lower states into the up-spin pass)
+    against the closed-form spectrum of free fermions on an open chain, levels
+    -2t cos(pi j / (Ns + 1)): FP64 within 1e-10 and mixed precision within 1e-6
+    of the exact energies; the FP64 states orthonormal, their residuals small,
+    and the oracle's (H psi_i)[J] equal to E_i psi_i[J] on sampled rows within
+    that residual."""
+    t = 1.0
+    edges = workload.chain(ns)
+    w = _free_spectrum([-2 * t * math.cos(math.pi * j / (ns + 1)) for j in range(1, ns + 1)], nu, nd)[:k]
+    _say("fused deflation", name, "exact", w)
+    h, E, res, Psi = _gpu_states(ns, edges, nu, nd, t, 0.0, k, hb.HUBBARD_FP64, tol=1e-14, max_iter=800)
+    assert h.dim >= 65536
+    _say("fp64 E", E, "iters", [r["n_iter"] for r in res], "residuals", [r["residual"] for r in res])
+    assert np.all(np.abs(E - w) <= 1e-10 * np.maximum(1.0, np.abs(w))), (E, w)
+    assert np.abs(Psi @ Psi.T - np.eye(k)).max() <= 1e-12
+    m = oracle.Model(ns, edges, nu, nd, t, 0.0)
+    rows = np.random.default_rng(SEED).choice(h.dim, 64, replace=False)
+    for i in range(k):
+        assert res[i]["residual"] <= 1e-6
+        hv = m.apply_rows(Psi[i], rows)
+        assert np.all(np.abs(hv - E[i] * Psi[i][rows]) <= res[i]["residual"] + 1e-12)
+    _, Em, resm, _ = _gpu_states(ns, edges, nu, nd, t, 0.0, k, hb.HUBBARD_MIXED, tol=1e-10, max_iter=800,
+                                 want_psi=False)
+    _say("mixed E", Em)
+    assert np.all(np.abs(Em - w) <= 1e-6 * np.maximum(1.0, np.abs(w))), (Em, w)
