@@ -460,18 +460,20 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
     auto counts = [&](int k) -> uint32_t {
         return wv + 16 * k < nchunk ? (uint32_t)__builtin_amdgcn_readlane((int)cnt_lane, k) : 0u;
     };
-    // a column's entry groups (all of them, so one memory round trip per column)
+    // a column's entry groups (all of them, so one memory round trip per
+    // column).  Every load is issued, slots past the column chunk's counts
+    // reading group 0 again (unused): with no skipped loads the wait counters
+    // stay exact, and using this column's groups never waits for the loads of
+    // the next one.
     auto load_groups = [&](int d, uint32_t c, uint4 (&ep)[NP], uint2 (&en)[NN], uint32_t &sd) {
         const int dd = d < ddn ? d : ddn - 1;
         const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
 #pragma unroll
         for (int g = 0; g < NP; g++)
-            if (g < np)
-                ep[g] = p.pidx[(size_t)g * (size_t)ddn + (size_t)dd];
+            ep[g] = p.pidx[(size_t)(g < np ? g : 0) * (size_t)ddn + (size_t)dd];
 #pragma unroll
         for (int g = 0; g < NN; g++)
-            if (g < nn)
-                en[g] = p.nidx[(size_t)g * (size_t)ddn + (size_t)dd];
+            en[g] = p.nidx[(size_t)(g < nn ? g : 0) * (size_t)ddn + (size_t)dd];
         sd = p.states_dn[dd];
     };
     int64_t r = blockIdx.x;
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
             uint2 enn[NN];
             uint32_t sdn = 0;
             constexpr bool ahead = !FUSED;  // the fused modes have no registers to spare
-            if (ahead && d0 + kRowThreads < ddn)
+            if (ahead)
                 load_groups(d + kRowThreads, cn, epn, enn, sdn);
             const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
             {
@@ -553,7 +555,7 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                 for (int g = 0; g < NN; g++)
                     en[g] = enn[g];
                 sd = sdn;
-            } else if (d0 + kRowThreads < ddn) {
+            } else {
                 load_groups(d + kRowThreads, cn, ep, en, sd);
             }
         }
