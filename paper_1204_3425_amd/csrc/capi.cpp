@@ -942,7 +942,7 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
     const size_t bbytes = sizeof(double) * (size_t)stride * (size_t)(m + 1);
     DevBuf basis(bbytes);
     HUB_HIP(hipMemsetAsync(basis.p, 0, bbytes, s));
-    DevBuf partials(sizeof(double) * (size_t)(std::max(2 * plan.nparts, 4096) + 64));
+    DevBuf partials(sizeof(double) * (size_t)(std::max(6 * plan.nparts, 4096) + 64));
     DevBuf scal(sizeof(double) * 4 * (size_t)(m + 2));
     DevBuf gamd(sizeof(double) * 2 * (size_t)m);
     PinnedBuf host(sizeof(double) * (4 * (size_t)(m + 2) + 2 * (size_t)m));
@@ -950,8 +950,23 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
     double *sc = scal.as<double>(), *B = basis.as<double>(), *part = partials.as<double>();
     auto slot = [&](int j) { return B + (size_t)j * (size_t)stride; };
 
+    // Fused form (two-pass plans with the line layout of the up-spin
+    // entries): step j's row pass forms w_j = q_{j-1} - c w_{j-1} in slot j
+    // while it stages the rows, as the ground-state step does, and writes
+    // s_j H w_j + beta w_{j-1} to slot j + 1; both halves run in the same
+    // launches and one reduction gives a_j and b_{j+1} (expanded norm).  The
+    // scalars then live in the ground-state layout S, the coefficients in
+    // hist (a_j, b_{j+1}) and the scale of each w_j in scl.  Other plans keep
+    // the separate update pass.
+    const bool fused = plan.two_pass && plan.blk_grid > 0 && args.up_line;
+    const int sb = stream_blocks(stride);
+    DevBuf fsc(sizeof(double) * (8 + kMaxDeflate + 1 + 2 * (size_t)m + (size_t)m + 8));
+    double *S = fsc.as<double>(), *hist = S + 8 + kMaxDeflate + 1, *scl = hist + 2 * m;
     int nb = launch_prop_load(re, im, B, npad, du, dd, ld, part, s);
-    launch_prop_reduce(part, nb, PROP_START, sc, 0, s);
+    if (fused)
+        launch_reduce_step(part, nb, RED_START, S, nullptr, 0, s);
+    else
+        launch_prop_reduce(part, nb, PROP_START, sc, 0, s);
     const double dt = t / n_steps;
     double err = 0.0;
     int mmax = 0;
@@ -959,6 +974,21 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
         // the round after the last step only measures <H> of the final state
         const int msteps = k < n_steps ? m : 1;
         for (int j = 0; j < msteps; j++) {
+            if (fused) {
+                // w_j is formed by this step's row pass; S[0] = 1/|w_j| until the reduction
+                HUB_HIP(hipMemcpyAsync(scl + j, S, sizeof(double), hipMemcpyDeviceToDevice, s));
+                // slot j - 1 feeds the beta and c terms (both 0 in step 0, any finite slot will do)
+                const int np = launch_hv2<double>(args, plan, slot(j), ld, slot(j > 0 ? j - 1 : j + 1), ld, nullptr,
+                                                  0, HV_FUSED, 0.0, S, part, s, nullptr, nullptr, nullptr,
+                                                  slot(j + 1), npad);
+                launch_reduce_step(part, np, RED_FUSED, S, hist, j, s);
+                if (k == n_steps)
+                    break;
+                // steps whose expanded norm lost its digits form w_{j+1} explicitly
+                launch_fused_fix<double>(slot(j + 1), slot(j), S, stride, part, sb, s);
+                launch_reduce_step(part, sb, RED_FIX, S, hist, j, s);
+                continue;
+            }
             const int np = launch_hv2<double>(args, plan, slot(j), ld, slot(j + 1), ld, nullptr, 0, HV_LANCZOS, 0.0,
                                               sc + 4 * j, part, s);
             const int np2 = launch_hv2<double>(args, plan, slot(j) + npad, ld, slot(j + 1) + npad, ld, nullptr, 0,
@@ -969,8 +999,23 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
             nb = launch_prop_update(slot(j + 1), slot(j), j > 0 ? slot(j - 1) : nullptr, sc, j, stride, part, s);
             launch_prop_reduce(part, nb, PROP_NORM, sc, j, s);
         }
-        HUB_HIP(hipMemcpyAsync(sh, sc, sizeof(double) * 4 * (size_t)(msteps + 1), hipMemcpyDeviceToHost, s));
-        HUB_HIP(hipStreamSynchronize(s));
+        if (fused) {
+            // the same host view as the unfused form: {s_j, -, a_j, b_{j+1}} per step
+            std::vector<double> fh(3 * (size_t)msteps);
+            HUB_HIP(hipMemcpyAsync(fh.data(), hist, sizeof(double) * 2 * (size_t)msteps, hipMemcpyDeviceToHost, s));
+            HUB_HIP(hipMemcpyAsync(fh.data() + 2 * msteps, scl, sizeof(double) * (size_t)msteps,
+                                   hipMemcpyDeviceToHost, s));
+            HUB_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < msteps; j++) {
+                sh[4 * j] = fh[2 * (size_t)msteps + (size_t)j];
+                sh[4 * j + 1] = 0.0;
+                sh[4 * j + 2] = fh[2 * (size_t)j];
+                sh[4 * j + 3] = fh[2 * (size_t)j + 1];
+            }
+        } else {
+            HUB_HIP(hipMemcpyAsync(sh, sc, sizeof(double) * 4 * (size_t)(msteps + 1), hipMemcpyDeviceToHost, s));
+            HUB_HIP(hipStreamSynchronize(s));
+        }
         if (!(sh[0] > 0.0) || !std::isfinite(sh[0]))
             fail(k == 0 ? HUBBARD_EINVAL : HUBBARD_EDEVICE, "psi has zero or non-finite norm");
         if (energy)
@@ -1005,7 +1050,10 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
         }
         HUB_HIP(hipMemcpyAsync(gamd.p, gh, sizeof(double) * 2 * (size_t)nv, hipMemcpyHostToDevice, s));
         nb = launch_prop_combine(B, nv, stride, npad, gamd.as<double>(), re, im, du, dd, ld, part, s);
-        launch_prop_reduce(part, nb, PROP_START, sc, 0, s);
+        if (fused)
+            launch_reduce_step(part, nb, RED_START, S, nullptr, 0, s);
+        else
+            launch_prop_reduce(part, nb, PROP_START, sc, 0, s);
         mmax = std::max(mmax, nv);
     }
     auto t1 = std::chrono::steady_clock::now();

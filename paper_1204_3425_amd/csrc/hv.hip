@@ -98,6 +98,8 @@ struct RowArgs {
     void *xc;       // null, or rows at stride ldc that receive a copy of each staged row
     int64_t ldc;
     HvDefl defl;    // HV_FUSED_DEFL
+    void *yo;       // fused modes: null (y is overwritten), or rows at stride ldyo for the result
+    int64_t ldyo;
 };
 
 // Per-bond amplitudes (GT kernels): entries carry a class of at most four
@@ -274,6 +276,8 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
                         T *yp = y + (r0 + q) * ldy + d;
                         if (MODE == HV_STORE)
                             *yp = hx;
+                        else if (FUSED && p.yo)
+                            static_cast<T *>(p.yo)[(r0 + q) * p.ldyo + d] = a_s * hx + b_s * *yp;
                         else if (MODE == HV_LANCZOS || FUSED)
                             *yp = a_s * hx + b_s * *yp;
                         else
@@ -316,6 +320,8 @@ struct Row64Args {
     double *xc;  // null, or rows at stride ldc that receive a copy of each staged row
     int64_t ldc;
     HvDefl defl;  // HV_FUSED_DEFL
+    double *yo;   // fused modes: null (y is overwritten), or rows at stride ldyo for the result
+    int64_t ldyo;
 };
 
 __device__ inline uint32_t lds_off_lo(uint32_t e)
@@ -540,6 +546,8 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                     double *yp = y + r * ldy + d;
                     if (MODE == HV_STORE)
                         *yp = hx;
+                    else if (FUSED && p.yo)
+                        p.yo[r * p.ldyo + d] = alpha * hx + beta * *yp;
                     else if (MODE == HV_LANCZOS || FUSED)
                         *yp = alpha * hx + beta * *yp;
                     else
@@ -875,6 +883,9 @@ struct LineArgs {
     int64_t ldyo;
     int yoal;      // alignment of the result rows: 16 or 8 bytes (vector stores), else 0
     HvDefl defl;   // HV_FUSED_DEFL: the lower vectors psi_l . y and psi_l . x are summed against
+    int64_t pair;  // 0, or the element offset of a second vector pair (x, y, result): workgroups
+                   // from gpair on take it, and the partial sums cover both
+    int gpair;
 };
 
 // Blocked slab pass, line layout (rows of at most 64 hops).  Same workgroup
@@ -929,8 +940,16 @@ __global__ __launch_bounds__(1024) void hv_lines_kernel(LineArgs p, const T *__r
     const T am[4] = {(T)p.amp[0], (T)p.amp[1], (T)p.amp[2], (T)p.amp[3]};
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwave = blockDim.x >> 6;
-    const int xcd = blockIdx.x & 7;
-    const int local = blockIdx.x >> 3;
+    int bid = (int)blockIdx.x;
+    if (p.pair && bid >= p.gpair) {
+        // the second vector pair (the imaginary halves of a complex vector)
+        bid -= p.gpair;
+        x += p.pair;
+        y += p.pair;
+        p.yo = static_cast<T *>(p.yo) + p.pair;
+    }
+    const int xcd = bid & 7;
+    const int local = bid >> 3;
     // slab-major per XCD: XCD k takes slabs k, k + 8, ... (rows on 128 bytes),
     // or the k-th contiguous range of slabs, so that the cache lines two
     // neighbouring slabs share stay in one L2 (rows not on 128 bytes)
@@ -1368,12 +1387,14 @@ static void launch_rows64_mode(const Row64Args &ra, int np, int nn, const HvPlan
 
 static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, int64_t ldx, double *y, int64_t ldy,
                           int mode, double alpha, const double *coef, hipStream_t s, double *xc, int64_t ldc,
-                          const HvDefl &defl)
+                          const HvDefl &defl, double *yo, int64_t ldyo)
 {
     Row64Args ra;
     ra.xc = xc;
     ra.ldc = ldc;
     ra.defl = defl;
+    ra.yo = yo;
+    ra.ldyo = ldyo;
     ra.pidx = a.dn_pidx;
     ra.nidx = a.dn_nidx;
     ra.pn = a.dn_pn;
@@ -1399,7 +1420,7 @@ static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, in
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s, T *xpad,
-               T *ypad, const HvDefl *defl)
+               T *ypad, const HvDefl *defl, T *yout, int64_t pair)
 {
     if (!pl.two_pass) {
         // rows too wide for LDS: the one-pass kernel (dense rows only)
@@ -1441,19 +1462,37 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     if (mode == HV_FUSED_DEFL && (gt || !a.up_line || !(dfl.nd >= 1 && dfl.nd <= kFusedDefl) || !dfl.psi || !dfl.g))
         fail(HUBBARD_EDEVICE, "fused deflated step: unsupported plan or deflation data");
     ra.defl = dfl;
+    const bool fusedm = mode == HV_FUSED || mode == HV_FUSED_DEFL;
+    if ((yout || pair) && !(fusedm && !repad && a.up_line))
+        fail(HUBBARD_EDEVICE, "a separate result and vector pairs need a fused step on the line layout");
+    ra.yo = yout;
+    ra.ldyo = ldy;
     if (repad && mode == HV_STORE) {
         yr = ypad;
         ldyr = pl.ld;
     }
-    if (sizeof(T) == 8 && row64_ok(a, pl))
-        launch_rows64(a, pl, reinterpret_cast<const double *>(x), ldx, reinterpret_cast<double *>(yr), ldyr, mode,
-                      alpha, coef, s, reinterpret_cast<double *>(ra.xc), ra.ldc, dfl);
-    else if (pl.rows_rpb == 3)
-        launch_rows_rpb<T, 3>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
-    else if (pl.rows_rpb == 2)
-        launch_rows_rpb<T, 2>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
-    else
-        launch_rows_rpb<T, 1>(ra, g16, gt, pl, x, ldx, yr, ldyr, mode, alpha, coef, s);
+    // the row pass, once per vector pair
+    for (int half = 0; half < (pair ? 2 : 1); half++) {
+        const int64_t o = half ? pair : 0;
+        RowArgs rh = ra;
+        if (yout)
+            rh.yo = yout + o;
+        if (sizeof(T) == 8 && row64_ok(a, pl))
+            launch_rows64(a, pl, reinterpret_cast<const double *>(x + o), ldx, reinterpret_cast<double *>(yr + o), ldyr,
+                          mode, alpha, coef, s, reinterpret_cast<double *>(ra.xc), ra.ldc, dfl,
+                          reinterpret_cast<double *>(rh.yo), ldy);
+        else if (pl.rows_rpb == 3)
+            launch_rows_rpb<T, 3>(rh, g16, gt, pl, x + o, ldx, yr + o, ldyr, mode, alpha, coef, s);
+        else if (pl.rows_rpb == 2)
+            launch_rows_rpb<T, 2>(rh, g16, gt, pl, x + o, ldx, yr + o, ldyr, mode, alpha, coef, s);
+        else
+            launch_rows_rpb<T, 1>(rh, g16, gt, pl, x + o, ldx, yr + o, ldyr, mode, alpha, coef, s);
+    }
+    if (yout) {
+        // the up-spin pass adds to the result rows
+        yr = yout;
+        yo = yout;
+    }
 
     if (repad) {
         x = xpad;
@@ -1500,6 +1539,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             la.yo = yo;
             la.ldyo = ldyo;
             la.defl = dfl;
+            la.pair = pair;
+            la.gpair = pl.blk_grid;
             la.yoal = ((uintptr_t)yo % 16 == 0 && ldyo % v16 == 0)                         ? 16
                       : ((uintptr_t)yo % 8 == 0 && (ldyo * (int64_t)sizeof(T)) % 8 == 0) ? 8
                                                                                          : 0;
@@ -1510,8 +1551,8 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                 if (pl.blk_lds > 64 * 1024)
                     HUB_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                 (int)pl.blk_lds));
-                hipLaunchKernelGGL(kern, dim3(pl.blk_grid), dim3(pl.blk_threads), pl.blk_lds, s, la, x, ldx, yr,
-                                   ldyr, alpha, coef, partials);
+                hipLaunchKernelGGL(kern, dim3(pl.blk_grid * (pair ? 2 : 1)), dim3(pl.blk_threads), pl.blk_lds, s, la,
+                                   x, ldx, yr, ldyr, alpha, coef, partials);
                 HUB_HIP(hipGetLastError());
             };
             // 32-bit external offsets: rows and row stride below 2^24, x below 4 GB
@@ -1550,7 +1591,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
                 pick(std::integral_constant<int, HV_FUSED_DEFL>{});
             else
                 pick(std::integral_constant<int, HV_RESIDUAL>{});
-            return pl.blk_grid;
+            return pl.blk_grid * (pair ? 2 : 1);
         }
         if (mode == HV_STORE)
             gt ? gob(hv_blocks_kernel<T, HV_STORE, true>) : gob(hv_blocks_kernel<T, HV_STORE, false>);
@@ -1595,9 +1636,9 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
 
 template int launch_hv2<double>(const HvArgs &, const HvPlan &, const double *, int64_t, double *, int64_t, double *,
                                 int64_t, int, double, const double *, double *, hipStream_t, double *, double *,
-                                const HvDefl *);
+                                const HvDefl *, double *, int64_t);
 template int launch_hv2<float>(const HvArgs &, const HvPlan &, const float *, int64_t, float *, int64_t, float *,
                                int64_t, int, double, const double *, double *, hipStream_t, float *, float *,
-                               const HvDefl *);
+                               const HvDefl *, float *, int64_t);
 
 }  // namespace hub

@@ -223,10 +223,15 @@ HvPlan make_hv_plan(const HvArgs &a, int elem_bytes);
 // not start on 128 bytes, HV_STORE with both (HV_RESIDUAL with xpad) routes
 // through them: the row pass writes its result to ypad (scratch) and a copy
 // of x to xpad, and the up-spin pass runs on those and writes y.
+// yout (fused modes, line layout): the result goes to yout (stride ldy) and y
+// is only read (the beta and c terms).  pair > 0: the same step on a second
+// vector pair at element offset pair from x, y and yout (the imaginary halves
+// of complex vectors); the partial sums cover both pairs.
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s,
-               T *xpad = nullptr, T *ypad = nullptr, const HvDefl *defl = nullptr);
+               T *xpad = nullptr, T *ypad = nullptr, const HvDefl *defl = nullptr, T *yout = nullptr,
+               int64_t pair = 0);
 
 template <typename T>
 void launch_axpy_norm(T *w, const T *v, const double *coef, int64_t n, double *partials, int nblocks, hipStream_t s);
