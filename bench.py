@@ -662,8 +662,9 @@ def stored_traffic(dim):
 
 def _kernel_family(name):
     for fam in ("batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "batch_init_state_kernel",
-                "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel", "hv_kernel",
-                "axpy_norm_kernel", "defl_dots_kernel", "defl_update_kernel", "obs_accumulate_kernel",
+                "hv_rows64_kernel", "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel",
+                "hv_kernel", "axpy_norm_kernel", "fused_fix_defl_kernel", "fused_fix_kernel", "defl_dots_kernel",
+                "defl_update_kernel", "obs_accumulate_kernel",
                 "obs_sum_groups_kernel", "obs_sum_kernel", "psi_stats_kernel", "scale_kernel",
                 "prop_load_kernel", "prop_update_kernel", "prop_combine_kernel", "prop_reduce_kernel",
                 "reduce_kernel", "start_fill_kernel", "start_norm2_kernel", "start_raw_kernel", "init_scalars_kernel",
@@ -672,10 +673,16 @@ def _kernel_family(name):
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""
             gt = ""
+            if fam == "hv_rows64_kernel":
+                # the FP64 one-row pass: template arguments MODE, VEC, CH, NP, NN
+                targs = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "").split(",")
+                mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused", "4": "fused-defl"}.get(
+                    targs[0], "")
+                return " ".join(x for x in (fam, "f64", mode) if x)
             if fam in ("hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel"):
                 targs = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "").split(",")
                 k = 2 if fam == "hv_rows_kernel" else 1
-                mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused"}.get(
+                mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused", "4": "fused-defl"}.get(
                     targs[k] if len(targs) > k else "", "")
                 # the per-bond variant: template argument 4 of the row pass, 2 of the others; the line
                 # pass also names its line width (32 or 64 slots)
@@ -747,8 +754,8 @@ def summarize_pmc(dfetch, dwrite):
         nw, bw = write.get(k, (0, 0.0))
         print("# %-34s %6d %14.4f %14.4f" % (k, max(nf, nw), bf * sf / 1e9, bw * sw / 1e9))
     hv = 0.0
-    for k in ("hv_rows_kernel f64 store", "hv_lines_kernel f64 store", "hv_blocks_kernel f64 store",
-              "hv_slabs_kernel f64 store"):
+    for k in ("hv_rows64_kernel f64 store", "hv_rows_kernel f64 store", "hv_lines_kernel f64 store",
+              "hv_blocks_kernel f64 store", "hv_slabs_kernel f64 store"):
         hv += fetch.get(k, (0, 0.0))[1] * sf + write.get(k, (0, 0.0))[1] * sw
     import workload
     print("source_sha", source_hash())
@@ -773,6 +780,8 @@ def main():
                     help="requests of the closed-loop run that sets the arrival rate")
     ap.add_argument("--oracle-worker", help=argparse.SUPPRESS)
     ap.add_argument("--no-small", action="store_true", help="skip the 14-site and 8-site ring legs")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip timing hubbard_apply on dense vectors (the traffic counters then see padded rows only)")
     ap.add_argument("--propagate", type=int, default=1, help="real-time propagation leg (0 skips it)")
     ap.add_argument("--bonds", type=int, default=1, help="per-bond amplitude leg (0 skips it)")
     ap.add_argument("--excited", type=int, default=3,
@@ -814,7 +823,7 @@ def main():
     for name, prec, es in (("fp64", hb.HUBBARD_FP64, 8), ("mixed", hb.HUBBARD_MIXED, 4)):
         log("timing H.v", name)
         t_hv = time_hv(hb, torch, h, prec, max(10, args.steps // 4), 3)
-        t_dense = time_hv_dense(hb, torch, h, prec, max(10, args.steps // 4), 3)
+        t_dense = None if args.no_dense else time_hv_dense(hb, torch, h, prec, max(10, args.steps // 4), 3)
         log("timing Lanczos", name, args.steps, "steps")
         t_lz, r = time_lanczos(hb, torch, h, prec, args.steps, args.warmup, p.seed)
         res[name] = {"hv_s": t_hv, "hv_dense_s": t_dense, "hv_gbs": 2.0 * p.dim * es / t_hv / 1e9, "lanczos_s": t_lz,
@@ -852,7 +861,8 @@ def main():
         "lanczos_iters_per_s": {k: round(v["iters"] / v["lanczos_s"], 2) for k, v in res.items()},
         "lanczos_ms_per_iter": {k: round(v["lanczos_s"] / v["iters"] * 1e3, 4) for k, v in res.items()},
         "hv_us": {k: round(v["hv_s"] * 1e6, 1) for k, v in res.items()},
-        "hv_dense_apply_us": {k: round(v["hv_dense_s"] * 1e6, 1) for k, v in res.items()},
+        "hv_dense_apply_us": {k: (None if v["hv_dense_s"] is None else round(v["hv_dense_s"] * 1e6, 1))
+                              for k, v in res.items()},
         "hv_gbs": {k: round(v["hv_gbs"], 1) for k, v in res.items()},
         "E0": {k: v["E0"] for k, v in res.items()},
         "E0_rel_err_vs_oracle": e0_err,
@@ -863,7 +873,8 @@ def main():
                                      "between the L2 caches and the fabric, Infinity Cache hits included), "
                                      "scaled by the same counters on a device copy",
                      "traffic_over_algorithmic": None if traffic is None else round(traffic / (2 * p.dim * 8), 3),
-                     "kernel": "FP64 H.v = hv_rows_kernel + hv_lines_kernel (store mode, padded rows)",
+                     "kernel": "FP64 H.v = hv_rows64_kernel (row pass) + hv_lines_kernel (up-spin pass), "
+                               "store mode, padded rows",
                      "algorithmic_bytes_per_launch": 2 * p.dim * 8},
         "paper_context": PAPER_CONTEXT,
     }
