@@ -100,6 +100,7 @@ struct RowArgs {
     HvDefl defl;    // HV_FUSED_DEFL
     void *yo;       // fused modes: null (y is overwritten), or rows at stride ldyo for the result
     int64_t ldyo;
+    int gmax;       // group slots per column in the table used (groups of eight 16-bit or four 32-bit entries)
 };
 
 // Per-bond amplitudes (GT kernels): entries carry a class of at most four
@@ -138,7 +139,14 @@ __device__ inline T signed_factor(const T (&a)[4], uint32_t e)
 
 // Row pass.  MODE as in the file comment; for HV_RESIDUAL y is the scratch
 // vector z and alpha is the shift.
-template <typename T, int RPB, int MODE, bool G16, bool GT>
+// PF: every column's entries fit four groups (gmax <= 4), so the next column's
+// groups, count, down configuration and (modes that read it) y are loaded a
+// column ahead, every slot issued (past gmax: slot 0 again, unused; rows past
+// the block: its last row) so that the wait counters stay exact.
+// s_waitcnt vmcnt(0) with the other counters left alone (gfx9 encoding)
+constexpr int kVmcnt0 = 0x0f70;
+
+template <typename T, int RPB, int MODE, bool G16, bool GT, bool PF>
 __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__restrict__ x, int64_t ldx,
                                                        T *__restrict__ y, int64_t ldy, double alpha, double beta,
                                                        const double *__restrict__ coef)
@@ -218,74 +226,138 @@ __global__ __launch_bounds__(1024) void hv_rows_kernel(RowArgs p, const T *__res
         for (int q = 0; q < RPB; q++)
             su[q] = p.states_up[min(r0 + q, p.dim_up - 1)];
 
-        for (int64_t d0 = 0; d0 < ddn; d0 += blockDim.x) {
-            const int64_t d = d0 + threadIdx.x;
-            const bool ok = d < ddn;
-            const int64_t dd = ok ? d : ddn - 1;
-            const int nq = p.nq[dd >> 6];
-            const uint4 *__restrict__ gp = p.groups + dd;
-            T h[RPB];
+        // 32 entries per batch of table loads: 8 groups of four 32-bit
+        // entries, or 4 groups of eight 16-bit entries
+        constexpr int GB = G16 ? 4 : 8;
+        // one batch of groups: the hops of entries g0 * (G16 ? 8 : 4) on
+        auto batch = [&](int g0, int nq, const auto &e4, T (&h)[RPB]) {
+            constexpr int N = (int)(sizeof(e4) / sizeof(uint4));
 #pragma unroll
-            for (int q = 0; q < RPB; q++)
-                h[q] = (T)0;
-            // 32 entries per batch of table loads: 8 groups of four 32-bit
-            // entries, or 4 groups of eight 16-bit entries
-            constexpr int GB = G16 ? 4 : 8;
-            for (int g0 = 0; g0 < nq; g0 += GB) {
-                uint4 e4[GB];
+            for (int g = 0; g < N; g++) {
+                if (g0 + g < nq) {
+                    const uint32_t ev[4] = {e4[g].x, e4[g].y, e4[g].z, e4[g].w};
 #pragma unroll
-                for (int g = 0; g < GB; g++)
-                    if (g0 + g < nq)
-                        e4[g] = gp[(int64_t)(g0 + g) * ddn];
+                    for (int u = 0; u < (G16 ? 8 : 4); u++) {
+                        uint32_t off, sg;
+                        if (G16) {
+                            const uint32_t e = (ev[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
+                            off = (e & 0x7fffu) * (uint32_t)sizeof(T);
+                            sg = (e & 0x8000u) << 16;
+                        } else {
+                            off = ev[u] & (GT ? 0x3ffffu : 0x7fffffffu);
+                            sg = ev[u] & 0x80000000u;
+                        }
+                        const T ac = GT ? class_amp(am, (ev[u] >> 18) & 3u) : (T)1;
 #pragma unroll
-                for (int g = 0; g < GB; g++) {
-                    if (g0 + g < nq) {
-                        const uint32_t ev[4] = {e4[g].x, e4[g].y, e4[g].z, e4[g].w};
-#pragma unroll
-                        for (int u = 0; u < (G16 ? 8 : 4); u++) {
-                            uint32_t off, sg;
-                            if (G16) {
-                                const uint32_t e = (ev[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
-                                off = (e & 0x7fffu) * (uint32_t)sizeof(T);
-                                sg = (e & 0x8000u) << 16;
-                            } else {
-                                off = ev[u] & (GT ? 0x3ffffu : 0x7fffffffu);
-                                sg = ev[u] & 0x80000000u;
-                            }
-                            const T ac = GT ? class_amp(am, (ev[u] >> 18) & 3u) : (T)1;
-#pragma unroll
-                            for (int q = 0; q < RPB; q++) {
-                                const T v = *reinterpret_cast<const T *>(
-                                    reinterpret_cast<const unsigned char *>(xs + q * slot) + off);
-                                if (GT)
-                                    h[q] += ac * flip_sign(v, sg);
-                                else
-                                    h[q] += flip_sign(v, sg);
-                            }
+                        for (int q = 0; q < RPB; q++) {
+                            const T v = *reinterpret_cast<const T *>(
+                                reinterpret_cast<const unsigned char *>(xs + q * slot) + off);
+                            if (GT)
+                                h[q] += ac * flip_sign(v, sg);
+                            else
+                                h[q] += flip_sign(v, sg);
                         }
                     }
                 }
             }
-            if (ok) {
-                const uint32_t sd = p.states_dn[d];
+        };
+        // a column's groups, group count, down configuration and y values (PF)
+        constexpr int PB = 4;
+        constexpr bool YR = MODE == HV_LANCZOS || FUSED;  // the result reads y
+        auto fetch = [&](int64_t dcol, uint4 (&e4)[PB], int &nq, uint32_t &sdc, T (&yv)[RPB]) {
+            const int64_t dd = dcol < ddn ? dcol : ddn - 1;
+            nq = p.nq[dd >> 6];
 #pragma unroll
-                for (int q = 0; q < RPB; q++) {
-                    if (q < nr) {
-                        const T xv = xs[q * slot + d];
-                        const T hx = fma(mt, h[q], U * (T)__popc(su[q] & sd) * xv);
-                        T *yp = y + (r0 + q) * ldy + d;
-                        if (MODE == HV_STORE)
-                            *yp = hx;
-                        else if (FUSED && p.yo)
-                            static_cast<T *>(p.yo)[(r0 + q) * p.ldyo + d] = a_s * hx + b_s * *yp;
-                        else if (MODE == HV_LANCZOS || FUSED)
-                            *yp = a_s * hx + b_s * *yp;
-                        else
-                            *yp = hx - a_s * xv;
+            for (int g = 0; g < PB; g++)
+                e4[g] = p.groups[(int64_t)(g < p.gmax ? g : 0) * ddn + dd];
+            sdc = p.states_dn[dd];
+#pragma unroll
+            for (int q = 0; q < RPB; q++)
+                if (YR)
+                    yv[q] = y[(r0 + (q < nr ? q : nr - 1)) * ldy + dd];
+        };
+        // FULL (PF and a whole block of rows): the result is stored without a
+        // branch, lanes past the row's end repeating its last column (the same
+        // groups, counts and y value, so the same value to the same address),
+        // so the wait for the next column's loads never waits for these stores
+        auto cols = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            uint4 ec[PB];
+            int nqc = 0;
+            uint32_t sdc = 0;
+            T yc[RPB] = {};
+            if (PF) {
+                fetch(threadIdx.x, ec, nqc, sdc, yc);
+                // these loads complete before the loop: entered with them in
+                // flight, the loop would wait for all of its own memory
+                // operations (the stores included) at the top of every column
+                __builtin_amdgcn_s_waitcnt(kVmcnt0);
+            }
+            // a wave stops after its last chunk that holds a column of the row,
+            // so the lanes that repeat the last column sit in that column's wave
+            // (and read y there before it is written)
+            for (int64_t d0 = 0; d0 + (int64_t)(threadIdx.x & ~63u) < ddn; d0 += blockDim.x) {
+                const int64_t d = d0 + threadIdx.x;
+                const bool ok = d < ddn;
+                const int64_t dd = ok ? d : ddn - 1;
+                T h[RPB];
+#pragma unroll
+                for (int q = 0; q < RPB; q++)
+                    h[q] = (T)0;
+                uint32_t sd = sdc;
+                T yr[RPB];
+#pragma unroll
+                for (int q = 0; q < RPB; q++)
+                    yr[q] = yc[q];
+                if (PF) {
+                    uint4 en[PB];
+                    int nqn;
+                    uint32_t sdn;
+                    fetch(d + blockDim.x, en, nqn, sdn, yc);
+                    batch(0, nqc, ec, h);
+#pragma unroll
+                    for (int g = 0; g < PB; g++)
+                        ec[g] = en[g];
+                    nqc = nqn;
+                    sdc = sdn;
+                } else {
+                    const int nq = p.nq[dd >> 6];
+                    const uint4 *__restrict__ gp = p.groups + dd;
+                    for (int g0 = 0; g0 < nq; g0 += GB) {
+                        uint4 e4[GB];
+#pragma unroll
+                        for (int g = 0; g < GB; g++)
+                            if (g0 + g < nq)
+                                e4[g] = gp[(int64_t)(g0 + g) * ddn];
+                        batch(g0, nq, e4, h);
+                    }
+                    sd = p.states_dn[dd];
+                }
+                if (FULL || ok) {
+#pragma unroll
+                    for (int q = 0; q < RPB; q++) {
+                        if (FULL || q < nr) {
+                            const T xv = xs[q * slot + dd];
+                            const T hx = fma(mt, h[q], U * (T)__popc(su[q] & sd) * xv);
+                            T *yp = y + (r0 + q) * ldy + dd;
+                            const T yv = PF ? yr[q] : (YR ? *yp : (T)0);
+                            if (MODE == HV_STORE)
+                                *yp = hx;
+                            else if (FUSED && p.yo)
+                                static_cast<T *>(p.yo)[(r0 + q) * p.ldyo + dd] = a_s * hx + b_s * yv;
+                            else if (YR)
+                                *yp = a_s * hx + b_s * yv;
+                            else
+                                *yp = hx - a_s * xv;
+                        }
                     }
                 }
             }
-        }
+        };
+        if (PF && nr == RPB)
+            cols(std::true_type());
+        else
+            cols(std::false_type());
         __syncthreads();
     }
 }
@@ -458,14 +530,13 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
 
     const double mt = -p.t, U = p.U;
     // lane k holds the group counts of this wave's k-th column chunk (chunk
-    // wave + 16 k); a wave takes at most 64 chunks (rows of up to 65,536 elements)
+    // wave + 16 k); a wave takes at most 64 chunks (rows of up to 65,536
+    // elements).  Chunks past the row's end take the last chunk's counts: their
+    // lanes repeat the row's last column (below).
     const int wv = tid >> 6, nchunk = (ddn + 63) >> 6;
-    uint32_t cnt_lane = 0;
-    if (wv + 16 * lane < nchunk)
-        cnt_lane = *reinterpret_cast<const uint16_t *>(p.pn + 2 * (wv + 16 * lane));
-    auto counts = [&](int k) -> uint32_t {
-        return wv + 16 * k < nchunk ? (uint32_t)__builtin_amdgcn_readlane((int)cnt_lane, k) : 0u;
-    };
+    const uint32_t cnt_lane =
+        *reinterpret_cast<const uint16_t *>(p.pn + 2 * min(wv + 16 * lane, nchunk - 1));
+    auto counts = [&](int k) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)cnt_lane, k); };
     // a column's entry groups (all of them, so one memory round trip per
     // column).  Every load is issued, slots past the column chunk's counts
     // reading group 0 again (unused): with no skipped loads the wait counters
@@ -488,17 +559,22 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
     for (; r < p.dim_up; r += gridDim.x) {
         store_row(r);
         __syncthreads();
-        // the next row's loads stay in flight while this one is gathered
-        if (r + gridDim.x < p.dim_up)
-            load_row(r + gridDim.x);
         const uint32_t su = p.states_up[r];
         uint32_t c = counts(0);
         uint4 ep[NP];
         uint2 en[NN];
         uint32_t sd = 0;
         load_groups(tid, c, ep, en, sd);
+        // the next row's loads stay in flight while this one is gathered;
+        // issued after the first column's groups, so that the wait for those
+        // (the counters complete in order) does not wait for the row
+        if (r + gridDim.x < p.dim_up)
+            load_row(r + gridDim.x);
         int k = 0;
-        for (int d0 = 0; d0 < ddn; d0 += kRowThreads, k++) {
+        // a wave stops after its last chunk that holds a column of the row, so
+        // the lanes that repeat the last column sit in that column's wave (and
+        // read y there before it is written)
+        for (int d0 = 0; d0 + (wv << 6) < ddn; d0 += kRowThreads, k++) {
             const int d = d0 + tid;
             // the next column's entries load while this one is gathered
             const uint32_t cn = counts(k + 1);
@@ -508,6 +584,11 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
             constexpr bool ahead = !FUSED;  // the fused modes have no registers to spare
             if (ahead)
                 load_groups(d + kRowThreads, cn, epn, enn, sdn);
+            // y at this column (modes that read it) loads while the column is gathered
+            constexpr bool YR = MODE == HV_LANCZOS || FUSED;
+            double yv = 0.0;
+            if (YR)
+                yv = y[r * ldy + (d < ddn ? d : ddn - 1)];
             const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
             {
                 double h0 = 0.0, h1 = 0.0;
@@ -540,16 +621,21 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
                         h1 -= xv[3];
                     }
                 }
-                if (d < ddn) {
-                    const double xd = xs[d];
+                // every lane stores: lanes past the row's end repeat its last
+                // column (the same groups, counts and value, to the same
+                // address), so no store is skipped and the wait for the next
+                // column's loads never waits for this one's store
+                {
+                    const int dd = d < ddn ? d : ddn - 1;
+                    const double xd = xs[dd];
                     const double hx = fma(mt, h0 + h1, U * (double)__popc(su & sd) * xd);
-                    double *yp = y + r * ldy + d;
+                    double *yp = y + r * ldy + dd;
                     if (MODE == HV_STORE)
                         *yp = hx;
                     else if (FUSED && p.yo)
-                        p.yo[r * p.ldyo + d] = alpha * hx + beta * *yp;
-                    else if (MODE == HV_LANCZOS || FUSED)
-                        *yp = alpha * hx + beta * *yp;
+                        p.yo[r * p.ldyo + dd] = alpha * hx + beta * yv;
+                    else if (YR)
+                        *yp = alpha * hx + beta * yv;
                     else
                         *yp = hx - alpha * xd;
                 }
@@ -1306,39 +1392,39 @@ static void launch_rows_rpb(const RowArgs &ra, bool g16, bool gt, const HvPlan &
                            coef);
         HUB_HIP(hipGetLastError());
     };
-    if (gt) {
-        // per-bond amplitudes use the 32-bit groups (the class sits above the offset)
-        if (mode == HV_STORE)
-            go(hv_rows_kernel<T, RPB, HV_STORE, false, true>);
-        else if (mode == HV_LANCZOS)
-            go(hv_rows_kernel<T, RPB, HV_LANCZOS, false, true>);
-        else if (mode == HV_FUSED)
-            go(hv_rows_kernel<T, RPB, HV_FUSED, false, true>);
+    // a column's groups fit the four registers loaded a column ahead
+    const bool pf = ra.gmax <= 4;
+    auto pick = [&](auto mc, auto g16c, auto gtc) {
+        constexpr int M = decltype(mc)::value;
+        constexpr bool G16 = decltype(g16c)::value, GT = decltype(gtc)::value;
+        if constexpr (M == HV_FUSED_DEFL && GT)
+            fail(HUBBARD_EDEVICE, "fused deflated step: per-bond amplitudes unsupported");
+        else if (pf)
+            go(hv_rows_kernel<T, RPB, M, G16, GT, true>);
         else
-            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false, true>);
-    } else if (g16) {
+            go(hv_rows_kernel<T, RPB, M, G16, GT, false>);
+    };
+    using F = std::false_type;
+    using Tr = std::true_type;
+    auto by_mode = [&](auto g16c, auto gtc) {
         if (mode == HV_STORE)
-            go(hv_rows_kernel<T, RPB, HV_STORE, true, false>);
+            pick(std::integral_constant<int, HV_STORE>(), g16c, gtc);
         else if (mode == HV_LANCZOS)
-            go(hv_rows_kernel<T, RPB, HV_LANCZOS, true, false>);
+            pick(std::integral_constant<int, HV_LANCZOS>(), g16c, gtc);
         else if (mode == HV_FUSED)
-            go(hv_rows_kernel<T, RPB, HV_FUSED, true, false>);
+            pick(std::integral_constant<int, HV_FUSED>(), g16c, gtc);
         else if (mode == HV_FUSED_DEFL)
-            go(hv_rows_kernel<T, RPB, HV_FUSED_DEFL, true, false>);
+            pick(std::integral_constant<int, HV_FUSED_DEFL>(), g16c, gtc);
         else
-            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, true, false>);
-    } else {
-        if (mode == HV_STORE)
-            go(hv_rows_kernel<T, RPB, HV_STORE, false, false>);
-        else if (mode == HV_LANCZOS)
-            go(hv_rows_kernel<T, RPB, HV_LANCZOS, false, false>);
-        else if (mode == HV_FUSED)
-            go(hv_rows_kernel<T, RPB, HV_FUSED, false, false>);
-        else if (mode == HV_FUSED_DEFL)
-            go(hv_rows_kernel<T, RPB, HV_FUSED_DEFL, false, false>);
-        else
-            go(hv_rows_kernel<T, RPB, HV_RESIDUAL, false, false>);
-    }
+            pick(std::integral_constant<int, HV_RESIDUAL>(), g16c, gtc);
+    };
+    // per-bond amplitudes use the 32-bit groups (the class sits above the offset)
+    if (gt)
+        by_mode(F(), Tr());
+    else if (g16)
+        by_mode(Tr(), F());
+    else
+        by_mode(F(), F());
 }
 
 // The FP64 row pass takes handles of one amplitude whose rows need the whole
@@ -1442,6 +1528,7 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
     ra.dim_up = a.dim_up;
     ra.dim_dn = a.dim_dn;
     ra.ngroups = a.dn_ngroups;
+    ra.gmax = g16 ? std::max((a.w_dn + 7) / 8, 1) : std::max(a.dn_ngroups, 1);
     ra.t = a.t;
     ra.U = a.U;
     T *yr = mode == HV_RESIDUAL ? scratch : y;
