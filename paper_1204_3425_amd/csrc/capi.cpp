@@ -459,10 +459,15 @@ constexpr size_t kBasisChunk = 32;
 struct BasisPool {
     std::vector<std::unique_ptr<DevBuf>> chunks;
     size_t vb = 0;  // bytes per vector
+    // the padding of the rows (bytes pad_off..pitch of each row, rows per vector):
+    // zeroed when a chunk is allocated, since the kernels write only the row
+    // elements and the fix-up of a flagged fused step reads whole padded rows
+    size_t pitch = 0, pad_off = 0;
+    int64_t rows = 0;
     size_t capacity() const { return chunks.size() * kBasisChunk; }
     void *slot(size_t j) const { return static_cast<char *>(chunks[j / kBasisChunk]->p) + (j % kBasisChunk) * vb; }
     // room for vector j within budget (bytes the pool may hold in total); false when it cannot grow
-    bool reserve(size_t j, size_t budget)
+    bool reserve(size_t j, size_t budget, hipStream_t s)
     {
         while (j >= capacity()) {
             if ((chunks.size() + 1) * kBasisChunk * vb > budget)
@@ -473,6 +478,9 @@ struct BasisPool {
                 (void)hipGetLastError();
                 return false;
             }
+            if (pitch > pad_off)
+                HUB_HIP(hipMemset2DAsync(static_cast<char *>(chunks.back()->p) + pad_off, pitch, 0, pitch - pad_off,
+                                         (size_t)rows * kBasisChunk, s));
         }
         return true;
     }
@@ -579,6 +587,11 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
         return launch_hv2<T>(args, plan, C, ld, P, ld, nullptr, 0, fused ? HV_FUSED : HV_LANCZOS, 0.0,
                              fused ? S : S + 1, partials.as<double>(), s);
     };
+    // the same step with f_j formed in place in C, f_{j-1} in Pm and the result in Q
+    auto hv_step_slot = [&](T *C, T *Pm, T *Q) {
+        return launch_hv2<T>(args, plan, C, ld, Pm, ld, nullptr, 0, nd > 0 ? HV_FUSED_DEFL : HV_FUSED, 0.0, S,
+                             partials.as<double>(), s, nullptr, nullptr, nd > 0 ? &hdefl : nullptr, Q);
+    };
     auto finish_step = [&](T *C, T *P, int np, int j0) {
         if (fused) {
             launch_reduce_step(partials.as<double>(), np, RED_FUSED, S, hist, j0, s, nd);
@@ -639,6 +652,9 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
                 pool.chunks.clear();
             }
             pool.vb = vb;
+            pool.pitch = sizeof(T) * (size_t)ld;
+            pool.pad_off = sizeof(T) * (size_t)h->dn.dim;
+            pool.rows = h->up.dim;
         }
         size_t fr = 0, tot = 0;
         HUB_HIP(hipMemGetInfo(&fr, &tot));
@@ -650,7 +666,7 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
     auto keep = [&](const T *C, int j0) {
         if (!resident)
             return;
-        if (!pool.reserve((size_t)j0, basis_budget)) {
+        if (!pool.reserve((size_t)j0, basis_budget, s)) {
             resident = false;
             HUB_HIP(hipStreamSynchronize(s));
             pool.chunks.clear();
@@ -659,10 +675,29 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
         HUB_HIP(hipMemcpyAsync(pool.slot((size_t)j0), C, pool.vb, hipMemcpyDeviceToDevice, s));
         HUB_HIP(hipMemcpyAsync(scales.as<double>() + j0, S, sizeof(double), hipMemcpyDeviceToDevice, s));
     };
+    // Fused steps with psi requested (line layout) form each Lanczos vector in
+    // its slot: step j's row pass forms f_j in slot j from the q that step j-1
+    // left there and the H.v result goes to slot j + 1, so keeping a vector
+    // costs no copy.  When the pool cannot grow, the two live vectors move to
+    // the work vectors and the run goes on as without psi (psi by replay).
+    bool inslot = resident && fused && args.up_line && pool.reserve(1, basis_budget, s);
+    auto slotp = [&](int j) { return static_cast<T *>(pool.slot((size_t)j)); };
+    auto leave_slots = [&](int j0) {
+        // step j0 is next: q in slot j0, f_{j0-1} in slot j0 - 1
+        HUB_HIP(hipMemcpyAsync(vecs[j0 & 1], slotp(j0), pool.vb, hipMemcpyDeviceToDevice, s));
+        HUB_HIP(hipMemcpyAsync(vecs[(j0 + 1) & 1], slotp(j0 - 1), pool.vb, hipMemcpyDeviceToDevice, s));
+        HUB_HIP(hipStreamSynchronize(s));
+        pool.chunks.clear();
+        inslot = false;
+        resident = false;
+    };
 
     T *bufs[2] = {vecs[0], vecs[1]};
     auto t0 = std::chrono::steady_clock::now();
-    start_pass(bufs[0], bufs[1]);
+    if (inslot)
+        start_pass(slotp(0), bufs[1]);  // bufs[1]: zeros, the vector before f_1
+    else
+        start_pass(bufs[0], bufs[1]);
     if (nd > 0) {
         HUB_HIP(hipMemcpyAsync(hh, S, sizeof(double), hipMemcpyDeviceToHost, s));
         HUB_HIP(hipStreamSynchronize(s));
@@ -680,7 +715,14 @@ static void run_lanczos(hubbard *h, const hubbard_opts &o, LanczosOut &out, cons
         if (launched < max_iter) {
             const int j0 = launched;  // 0-based step index
             T *C = bufs[j0 & 1], *P = bufs[(j0 + 1) & 1];
-            if (fused) {
+            if (inslot && !pool.reserve((size_t)j0 + 1, basis_budget, s))
+                leave_slots(j0);
+            if (inslot) {
+                const int np = hv_step_slot(slotp(j0), j0 > 0 ? slotp(j0 - 1) : bufs[1], slotp(j0 + 1));
+                HUB_HIP(hipMemcpyAsync(scales.as<double>() + j0, S, sizeof(double), hipMemcpyDeviceToDevice, s));
+                // q is in slot j0 + 1, f_j0 in slot j0
+                finish_step(slotp(j0), slotp(j0 + 1), np, j0);
+            } else if (fused) {
                 // f_j exists once the step's row pass has formed it; S[0] still holds 1/s_j
                 const int np = hv_step(C, P);
                 keep(C, j0);

@@ -58,6 +58,22 @@ def test_basis_limit_reached_mid_run_falls_back():
     assert float((psi1 - psi5).abs().max()) <= 1e-12
 
 
+def test_fused_run_leaves_slots_mid_run():
+    """The 14-site ring takes the fused step with its vectors formed in their
+    slots; a limit of one chunk (32 vectors) runs out at step 32 of 87, where the
+    two live vectors move to the work vectors and psi comes from the replay.
+    The recurrence is the same arithmetic either way: coefficients bitwise."""
+    p = workload.ring14()
+    _say("slots left mid-run", p.name)
+    h = hb.hubbard_build(p.sites, p.edges, p.n_up, p.n_dn, p.t, p.U)
+    ld = hb.hubbard_info(h)["ld_pref"]
+    r32, psi32 = _solve(h, hb.HUBBARD_FP64, 32 * h.dim_up * ld * 8)
+    r1, psi1 = _solve(h, hb.HUBBARD_FP64, 2 ** 62)
+    assert r32["n_iter"] > 32 and r32["psi_resident"] == 0 and r1["psi_resident"] == 1
+    assert r32["E0"] == r1["E0"] and np.array_equal(r32["a"], r1["a"]) and np.array_equal(r32["b"], r1["b"])
+    assert float((psi1 - psi32).abs().max()) <= 1e-12
+
+
 def test_lowest_states_resident_and_replayed():
     h = hb.hubbard_build(8, workload.ring(8), 3, 3, 1.0, 4.0)
     out = []
