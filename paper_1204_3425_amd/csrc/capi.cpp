@@ -980,10 +980,21 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
     const int64_t ld = plan.ld, npad = h->up.dim * ld, stride = 2 * npad;
     const int64_t du = h->up.dim, dd = h->dn.dim;
     // the Krylov basis, resident: slot m receives the last H.v of a step.  The
-    // H.v runs with beta = 0 on the old contents of a slot, so they start as zeros.
+    // unfused H.v runs with beta = 0 on the old contents of a slot, so they start
+    // as zeros.  The fused step reads slot 1 with weight 0 in step 0 and writes
+    // only row elements, so there slot 1 and the rows' padding (which the
+    // fix-up of a flagged step reads) are the parts cleared.
     const size_t bbytes = sizeof(double) * (size_t)stride * (size_t)(m + 1);
     DevBuf basis(bbytes);
-    HUB_HIP(hipMemsetAsync(basis.p, 0, bbytes, s));
+    const bool fused = plan.two_pass && plan.blk_grid > 0 && args.up_line;
+    if (fused) {
+        HUB_HIP(hipMemsetAsync(static_cast<double *>(basis.p) + stride, 0, sizeof(double) * (size_t)stride, s));
+        if (ld > dd)
+            HUB_HIP(hipMemset2DAsync(static_cast<double *>(basis.p) + dd, sizeof(double) * (size_t)ld, 0,
+                                     sizeof(double) * (size_t)(ld - dd), 2 * (size_t)du * (size_t)(m + 1), s));
+    } else {
+        HUB_HIP(hipMemsetAsync(basis.p, 0, bbytes, s));
+    }
     DevBuf partials(sizeof(double) * (size_t)(std::max(6 * plan.nparts, 4096) + 64));
     DevBuf scal(sizeof(double) * 4 * (size_t)(m + 2));
     DevBuf gamd(sizeof(double) * 2 * (size_t)m);
@@ -1000,7 +1011,6 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
     // scalars then live in the ground-state layout S, the coefficients in
     // hist (a_j, b_{j+1}) and the scale of each w_j in scl.  Other plans keep
     // the separate update pass.
-    const bool fused = plan.two_pass && plan.blk_grid > 0 && args.up_line;
     const int sb = stream_blocks(stride);
     DevBuf fsc(sizeof(double) * (8 + kMaxDeflate + 1 + 2 * (size_t)m + (size_t)m + 8));
     double *S = fsc.as<double>(), *hist = S + 8 + kMaxDeflate + 1, *scl = hist + 2 * m;
@@ -1091,7 +1101,10 @@ int propagate_impl(hubbard *h, double *re, double *im, double t, int n_steps, in
             gh[2 * j + 1] = nrm * ci[(size_t)j] * sh[4 * j];
         }
         HUB_HIP(hipMemcpyAsync(gamd.p, gh, sizeof(double) * 2 * (size_t)nv, hipMemcpyHostToDevice, s));
-        nb = launch_prop_combine(B, nv, stride, npad, gamd.as<double>(), re, im, du, dd, ld, part, s);
+        // the caller's halves receive the state after the last step only
+        const bool last = k == n_steps - 1;
+        nb = launch_prop_combine(B, nv, stride, npad, gamd.as<double>(), last ? re : nullptr, last ? im : nullptr, du,
+                                 dd, ld, part, s);
         if (fused)
             launch_reduce_step(part, nb, RED_START, S, nullptr, 0, s);
         else

@@ -6,6 +6,7 @@
 // [re | im] in the padded row layout of the H.v (2 * npad doubles), and the
 // device scalars sc[4j..4j+3] = {s_j = 1/|w_j|, 0, a_j, b_{j+1}} let every step
 // launch without a host round trip (the H.v takes alpha = s_j, beta = 0).
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -74,9 +75,13 @@ __global__ __launch_bounds__(256) void prop_update_kernel(double *__restrict__ y
         partials[blockIdx.x] = s;
 }
 
-// psi = sum_{j < nv} gam_j w_j (complex gam_j = gam[2j] + i gam[2j+1]) into the
-// caller's dense halves and into slot 0 (the next step's start; each element is
-// read by its own thread before it is overwritten); partials of |psi|^2
+// psi = sum_{j < nv} gam_j w_j (complex gam_j = gam[2j] + i gam[2j+1]) into
+// slot 0 (the next step's start; each element is read by its own thread before
+// it is overwritten) and, after the last step (re, im not null), into the
+// caller's dense halves; partials of |psi|^2.  PAIR: a thread takes two
+// neighbouring elements of a row with 16-byte loads (even row stride; an odd
+// row's last pair reaches into the row's zero padding, which stays zero).
+template <bool PAIR>
 __global__ __launch_bounds__(256) void prop_combine_kernel(double *__restrict__ basis, int nv, int64_t slot_stride,
                                                            int64_t npad, const double *__restrict__ gam,
                                                            double *__restrict__ re, double *__restrict__ im,
@@ -84,22 +89,40 @@ __global__ __launch_bounds__(256) void prop_combine_kernel(double *__restrict__ 
                                                            double *__restrict__ partials)
 {
     __shared__ double red[4];
+    constexpr int E = PAIR ? 2 : 1;
+    typedef typename std::conditional<PAIR, double2, double>::type V;
     double acc = 0.0;
+    const int64_t nu = (dim_dn + E - 1) / E;
     for (int64_t r = blockIdx.x; r < dim_up; r += gridDim.x)
-        for (int64_t d = threadIdx.x; d < dim_dn; d += blockDim.x) {
-            const int64_t k = r * ld + d;
-            double pr = 0.0, pi = 0.0;
+        for (int64_t q = threadIdx.x; q < nu; q += blockDim.x) {
+            const int64_t d = q * E, k = r * ld + d;
+            double pr[E] = {}, pi[E] = {};
+#pragma unroll 4
             for (int j = 0; j < nv; j++) {
-                const double wr = basis[j * slot_stride + k], wi = basis[j * slot_stride + npad + k];
+                const V vr = *reinterpret_cast<const V *>(basis + j * slot_stride + k);
+                const V vi = *reinterpret_cast<const V *>(basis + j * slot_stride + npad + k);
+                const double *wr = reinterpret_cast<const double *>(&vr), *wi = reinterpret_cast<const double *>(&vi);
                 const double gr = gam[2 * j], gi = gam[2 * j + 1];
-                pr += gr * wr - gi * wi;
-                pi += gr * wi + gi * wr;
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    pr[e] += gr * wr[e] - gi * wi[e];
+                    pi[e] += gr * wi[e] + gi * wr[e];
+                }
             }
-            re[r * dim_dn + d] = pr;
-            im[r * dim_dn + d] = pi;
-            basis[k] = pr;
-            basis[npad + k] = pi;
-            acc += pr * pr + pi * pi;
+            V outr, outi;
+            double *orr = reinterpret_cast<double *>(&outr), *oii = reinterpret_cast<double *>(&outi);
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                orr[e] = pr[e];
+                oii[e] = pi[e];
+                acc += pr[e] * pr[e] + pi[e] * pi[e];
+                if (re && d + e < dim_dn) {
+                    re[r * dim_dn + d + e] = pr[e];
+                    im[r * dim_dn + d + e] = pi[e];
+                }
+            }
+            *reinterpret_cast<V *>(basis + k) = outr;
+            *reinterpret_cast<V *>(basis + npad + k) = outi;
         }
     const double s = prop_block_sum(acc, red);
     if (threadIdx.x == 0)
@@ -158,8 +181,13 @@ int launch_prop_combine(double *basis, int nv, int64_t slot_stride, int64_t npad
                         double *im, int64_t dim_up, int64_t dim_dn, int64_t ld, double *partials, hipStream_t s)
 {
     const int nb = prop_row_blocks(dim_up);
-    hipLaunchKernelGGL(prop_combine_kernel, dim3(nb), dim3(256), 0, s, basis, nv, slot_stride, npad, gam, re, im,
-                       dim_up, dim_dn, ld, partials);
+    const bool pair = ld % 2 == 0 && npad % 2 == 0 && slot_stride % 2 == 0;
+    if (pair)
+        hipLaunchKernelGGL(prop_combine_kernel<true>, dim3(nb), dim3(256), 0, s, basis, nv, slot_stride, npad, gam, re,
+                           im, dim_up, dim_dn, ld, partials);
+    else
+        hipLaunchKernelGGL(prop_combine_kernel<false>, dim3(nb), dim3(256), 0, s, basis, nv, slot_stride, npad, gam,
+                           re, im, dim_up, dim_dn, ld, partials);
     HUB_HIP(hipGetLastError());
     return nb;
 }
