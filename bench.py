@@ -662,7 +662,7 @@ def stored_traffic(dim):
 
 def _kernel_family(name):
     for fam in ("batch_hv_kernel", "batch_axpy_kernel", "batch_reduce_kernel", "batch_init_state_kernel",
-                "hv_rows64_kernel", "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel",
+                "hv_rows64_kernel", "hv_rows32x2_kernel", "hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel",
                 "hv_kernel", "axpy_norm_kernel", "fused_fix_defl_kernel", "fused_fix_kernel", "defl_dots_kernel",
                 "defl_update_kernel", "obs_accumulate_kernel",
                 "obs_sum_groups_kernel", "obs_sum_kernel", "psi_stats_kernel", "scale_kernel",
@@ -673,12 +673,12 @@ def _kernel_family(name):
             prec = "f64" if "<double" in name else ("f32" if "<float" in name else "")
             mode = ""
             gt = ""
-            if fam == "hv_rows64_kernel":
-                # the FP64 one-row pass: template arguments MODE, VEC, CH, NP, NN
+            if fam in ("hv_rows64_kernel", "hv_rows32x2_kernel"):
+                # the FP64 one-row pass and the FP32 row-pair pass: template arguments MODE, VEC, CH, NP, NN
                 targs = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "").split(",")
                 mode = {"0": "store", "1": "lanczos", "2": "residual", "3": "fused", "4": "fused-defl"}.get(
                     targs[0], "")
-                return " ".join(x for x in (fam, "f64", mode) if x)
+                return " ".join(x for x in (fam, "f64" if fam == "hv_rows64_kernel" else "f32", mode) if x)
             if fam in ("hv_rows_kernel", "hv_lines_kernel", "hv_blocks_kernel", "hv_slabs_kernel"):
                 targs = name.split("<", 1)[1].split(">", 1)[0].replace(" ", "").split(",")
                 k = 2 if fam == "hv_rows_kernel" else 1

@@ -657,6 +657,283 @@ __global__ __launch_bounds__(kRowThreads) void hv_rows64_kernel(Row64Args p, con
     }
 }
 
+// FP32 row pass on pairs of rows (one amplitude; rows of at most 13,312
+// elements).
+//
+// hv_rows64_kernel's product for two up configurations at once: rows r and
+// r + 1 sit in LDS interleaved, element e of both as one 8-byte pair, so one
+// gather at the FP64 kernel's address (the 16-bit index shifted by three)
+// fetches a hop's value for both rows and a table entry costs one shift, one
+// gather and two adds for two outputs.  The pair fills the LDS as one FP64 row
+// does.  Rows are staged in 8-byte units (two elements of a row), written to
+// LDS as 16 bytes (the two elements of both rows).  Modes as hv_rows64_kernel
+// without the deflated step.
+struct Row32Args {
+    const uint4 *__restrict__ pidx;  // [g][d] -> eight 16-bit element indices of + hops
+    const uint2 *__restrict__ nidx;  // [g][d] -> four 16-bit element indices of - hops
+    const uint8_t *__restrict__ pn;  // per 64 columns: + groups, - groups (two bytes)
+    const uint32_t *__restrict__ states_up;
+    const uint32_t *__restrict__ states_dn;
+    int64_t dim_up;
+    int dim_dn;
+    double t, U;
+    float *xc;  // null, or rows at stride ldc that receive a copy of each staged row
+    int64_t ldc;
+    float *yo;  // fused mode: null (y is overwritten), or rows at stride ldyo for the result
+    int64_t ldyo;
+};
+
+__device__ inline float2 lds_pair(const float2 *xs, uint32_t byte)
+{
+    return *reinterpret_cast<const float2 *>(reinterpret_cast<const unsigned char *>(xs) + byte);
+}
+
+template <int MODE, bool VEC, int CH, int NP, int NN>
+__global__ __launch_bounds__(kRowThreads) void hv_rows32x2_kernel(Row32Args p, const float *__restrict__ x,
+                                                                  int64_t ldx, float *__restrict__ y, int64_t ldy,
+                                                                  double alpha, double beta,
+                                                                  const double *__restrict__ coef)
+{
+    __shared__ __align__(16) float2 xs[kRow64Max + 2];
+    constexpr bool FUSED = MODE == HV_FUSED;
+    double cshift = 0.0;
+    if (MODE == HV_LANCZOS) {
+        alpha = coef[0];
+        beta = coef[1];
+    } else if (FUSED) {
+        alpha = coef[1];
+        beta = coef[2];
+        cshift = coef[3];
+    }
+    const float a_s = (float)alpha, b_s = (float)beta, c_s = (float)cshift;
+    const int ddn = p.dim_dn, tid = (int)threadIdx.x, lane = tid & 63;
+    const int64_t npair = (p.dim_up + 1) / 2;
+    // staging units: two elements of a row (rows on 8 bytes) or one element
+    typedef typename std::conditional<VEC, float2, float>::type SU;
+    const int nu = VEC ? ddn >> 1 : ddn;
+    const bool tail = VEC && (ddn & 1) && tid == kRowThreads - 1;  // the odd last element of a VEC row
+    SU v0[CH], v1[CH], w0[CH], w1[CH];
+    float vt0 = 0.f, vt1 = 0.f, wt0 = 0.f, wt1 = 0.f;
+    // units [0, PFU) of the next pair load while the current one is gathered,
+    // the rest when it is staged (registers for the whole pair would spill)
+    constexpr int PFU = VEC ? 3 : 5;
+    // units [u0, u1) of rows r and r1 of a pair (r1 = r for the last pair of an
+    // odd count: its second half is computed and not stored)
+    auto load_pair = [&](int64_t r, int64_t r1, int u0, int u1) {
+        const SU *s0 = reinterpret_cast<const SU *>(x + r * ldx);
+        const SU *s1 = reinterpret_cast<const SU *>(x + r1 * ldx);
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int i = u * kRowThreads + tid;
+            if (u >= u0 && u < u1 && i < nu) {
+                v0[u] = s0[i];
+                v1[u] = s1[i];
+            }
+        }
+        if (tail && u1 == CH) {
+            vt0 = x[r * ldx + ddn - 1];
+            vt1 = x[r1 * ldx + ddn - 1];
+        }
+    };
+    // the fused step's previous y, read when the pair is staged
+    auto load_prev = [&](int64_t r, int64_t r1) {
+        const SU *s0 = reinterpret_cast<const SU *>(y + r * ldy);
+        const SU *s1 = reinterpret_cast<const SU *>(y + r1 * ldy);
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int i = u * kRowThreads + tid;
+            if (i < nu) {
+                w0[u] = s0[i];
+                w1[u] = s1[i];
+            }
+        }
+        if (tail) {
+            wt0 = y[r * ldy + ddn - 1];
+            wt1 = y[r1 * ldy + ddn - 1];
+        }
+    };
+    auto store_pair = [&](int64_t r, int64_t r1, bool two) {
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int i = u * kRowThreads + tid;
+            if (i < nu) {
+                SU a = v0[u], b = v1[u];
+                if (FUSED) {
+                    // the q - a_j f_j update of the previous step, formed here and kept
+                    if constexpr (VEC) {
+                        a = make_float2(a.x - c_s * w0[u].x, a.y - c_s * w0[u].y);
+                        b = make_float2(b.x - c_s * w1[u].x, b.y - c_s * w1[u].y);
+                    } else {
+                        a = a - c_s * w0[u];
+                        b = b - c_s * w1[u];
+                    }
+                    reinterpret_cast<SU *>(const_cast<float *>(x) + r * ldx)[i] = a;
+                    if (two)
+                        reinterpret_cast<SU *>(const_cast<float *>(x) + r1 * ldx)[i] = b;
+                } else if (p.xc) {
+                    reinterpret_cast<SU *>(p.xc + r * p.ldc)[i] = a;
+                    if (two)
+                        reinterpret_cast<SU *>(p.xc + r1 * p.ldc)[i] = b;
+                }
+                if constexpr (VEC)
+                    reinterpret_cast<float4 *>(xs)[i] = make_float4(a.x, b.x, a.y, b.y);
+                else
+                    xs[i] = make_float2(a, b);
+            }
+        }
+        if (tail) {
+            float a = vt0, b = vt1;
+            if (FUSED) {
+                a = a - c_s * wt0;
+                b = b - c_s * wt1;
+                const_cast<float *>(x)[r * ldx + ddn - 1] = a;
+                if (two)
+                    const_cast<float *>(x)[r1 * ldx + ddn - 1] = b;
+            } else if (p.xc) {
+                p.xc[r * p.ldc + ddn - 1] = a;
+                if (two)
+                    p.xc[r1 * p.ldc + ddn - 1] = b;
+            }
+            xs[ddn - 1] = make_float2(a, b);
+        }
+        if (tid == 0)
+            xs[ddn] = make_float2(0.f, 0.f);  // the zero slot that padding entries point at
+    };
+
+    const float mt = (float)(-p.t), U = (float)p.U;
+    // counts of a wave's column chunks, one per lane (as in hv_rows64_kernel)
+    const int wv = tid >> 6, nchunk = (ddn + 63) >> 6;
+    const uint32_t cnt_lane =
+        *reinterpret_cast<const uint16_t *>(p.pn + 2 * min(wv + 16 * lane, nchunk - 1));
+    auto counts = [&](int k) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)cnt_lane, k); };
+    auto load_groups = [&](int d, uint32_t c, uint4 (&ep)[NP], uint2 (&en)[NN], uint32_t &sd) {
+        const int dd = d < ddn ? d : ddn - 1;
+        const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
+#pragma unroll
+        for (int g = 0; g < NP; g++)
+            ep[g] = p.pidx[(size_t)(g < np ? g : 0) * (size_t)ddn + (size_t)dd];
+#pragma unroll
+        for (int g = 0; g < NN; g++)
+            en[g] = p.nidx[(size_t)(g < nn ? g : 0) * (size_t)ddn + (size_t)dd];
+        sd = p.states_dn[dd];
+    };
+    int64_t pr = blockIdx.x;
+    if (pr < npair)
+        load_pair(2 * pr, min(2 * pr + 1, p.dim_up - 1), 0, PFU);
+    for (; pr < npair; pr += gridDim.x) {
+        const int64_t r = 2 * pr, r1 = min(r + 1, p.dim_up - 1);
+        const bool two = r + 1 < p.dim_up;
+        load_pair(r, r1, PFU, CH);
+        if (FUSED)
+            load_prev(r, r1);
+        store_pair(r, r1, two);
+        __syncthreads();
+        const uint32_t su0 = p.states_up[r], su1 = p.states_up[r1];
+        // the pair's rows of y (read) and of the result (uniform bases, so an
+        // access needs only the column offset)
+        const float *yin0 = y + r * ldy, *yin1 = y + r1 * ldy;
+        float *yout0 = (FUSED && p.yo) ? p.yo + r * p.ldyo : y + r * ldy;
+        float *yout1 = (FUSED && p.yo) ? p.yo + r1 * p.ldyo : y + r1 * ldy;
+        uint32_t c = counts(0);
+        uint4 ep[NP];
+        uint2 en[NN];
+        uint32_t sd = 0;
+        load_groups(tid, c, ep, en, sd);
+        if (pr + gridDim.x < npair)
+            load_pair(2 * (pr + gridDim.x), min(2 * (pr + gridDim.x) + 1, p.dim_up - 1), 0, PFU);
+        int k = 0;
+        for (int d0 = 0; d0 + (wv << 6) < ddn; d0 += kRowThreads, k++) {
+            const int d = d0 + tid;
+            const uint32_t cn = counts(k + 1);
+            uint4 epn[NP];
+            uint2 enn[NN];
+            uint32_t sdn = 0;
+            // the next column's groups load after this one's gathers: loaded a
+            // column ahead they would need registers the pair does not leave
+            constexpr bool ahead = false;
+            if (ahead)
+                load_groups(d + kRowThreads, cn, epn, enn, sdn);
+            constexpr bool YR = MODE == HV_LANCZOS || FUSED;
+            const int dd = d < ddn ? d : ddn - 1;
+            float yv0 = 0.f, yv1 = 0.f;
+            if (YR) {
+                yv0 = yin0[dd];
+                yv1 = yin1[dd];
+            }
+            const int np = (int)(c & 0xffu), nn = (int)(c >> 8);
+            float2 h0 = make_float2(0.f, 0.f), h1 = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int g = 0; g < NP; g++) {
+                if (g < np) {
+                    const uint32_t ev[4] = {ep[g].x, ep[g].y, ep[g].z, ep[g].w};
+                    float2 xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+                        xv[u] = lds_pair(xs, (u & 1) ? lds_off_hi(ev[u >> 1]) : lds_off_lo(ev[u >> 1]));
+#pragma unroll
+                    for (int u = 0; u < 8; u += 2) {
+                        h0.x += xv[u].x;
+                        h0.y += xv[u].y;
+                        h1.x += xv[u + 1].x;
+                        h1.y += xv[u + 1].y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < NN; g++) {
+                if (g < nn) {
+                    const uint32_t ev[2] = {en[g].x, en[g].y};
+                    float2 xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        xv[u] = lds_pair(xs, (u & 1) ? lds_off_hi(ev[u >> 1]) : lds_off_lo(ev[u >> 1]));
+#pragma unroll
+                    for (int u = 0; u < 4; u += 2) {
+                        h0.x -= xv[u].x;
+                        h0.y -= xv[u].y;
+                        h1.x -= xv[u + 1].x;
+                        h1.y -= xv[u + 1].y;
+                    }
+                }
+            }
+            // every lane stores (lanes past the row's end repeat its last
+            // column); the second row of an odd count's last pair is not stored
+            {
+                const float2 xd = xs[dd];
+                const float hx0 = fmaf(mt, h0.x + h1.x, U * (float)__popc(su0 & sd) * xd.x);
+                const float hx1 = fmaf(mt, h0.y + h1.y, U * (float)__popc(su1 & sd) * xd.y);
+                float o0, o1;
+                if (MODE == HV_STORE) {
+                    o0 = hx0;
+                    o1 = hx1;
+                } else if (YR) {
+                    o0 = a_s * hx0 + b_s * yv0;
+                    o1 = a_s * hx1 + b_s * yv1;
+                } else {
+                    o0 = hx0 - a_s * xd.x;
+                    o1 = hx1 - a_s * xd.y;
+                }
+                yout0[dd] = o0;
+                if (two)
+                    yout1[dd] = o1;
+            }
+            c = cn;
+            if (ahead) {
+#pragma unroll
+                for (int g = 0; g < NP; g++)
+                    ep[g] = epn[g];
+#pragma unroll
+                for (int g = 0; g < NN; g++)
+                    en[g] = enn[g];
+                sd = sdn;
+            } else {
+                load_groups(d + kRowThreads, cn, ep, en, sd);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 struct SlabArgs {
     const uint32_t *__restrict__ up_rows;  // row-major entries (column | sign<<31)
     const uint16_t *__restrict__ nnz_up;
@@ -1503,6 +1780,80 @@ static void launch_rows64(const HvArgs &a, const HvPlan &pl, const double *x, in
         launch_rows64_mode<HV_RESIDUAL>(ra, np, nn, pl, x, ldx, y, ldy, alpha, coef, s);
 }
 
+// The FP32 row pass on row pairs (hv_rows32x2_kernel): the same tables and
+// conditions as the FP64 row pass (one amplitude, 16-bit indices, at most 32
+// hops per column), any mode but the deflated step; one workgroup per CU.
+static bool rows32x2_ok(const HvArgs &a, int mode)
+{
+    return a.tcls == nullptr && a.dn_pidx != nullptr && a.w_dn <= 32 && a.dim_dn <= 13 * kRowThreads &&
+           mode != HV_FUSED_DEFL;
+}
+
+template <int MODE, bool VEC, int CH>
+static void launch_rows32x2_groups(const Row32Args &ra, int np, int nn, const float *x, int64_t ldx, float *y,
+                                   int64_t ldy, double alpha, const double *coef, hipStream_t s)
+{
+    const int64_t npair = (ra.dim_up + 1) / 2;
+    const int grid = (int)(npair < 256 ? npair : 256);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kRowThreads), 0, s, ra, x, ldx, y, ldy, alpha, 0.0, coef);
+        HUB_HIP(hipGetLastError());
+    };
+    if (np <= 3 && nn <= 4)
+        go(hv_rows32x2_kernel<MODE, VEC, CH, 3, 4>);
+    else
+        go(hv_rows32x2_kernel<MODE, VEC, CH, 4, 8>);
+}
+
+template <int MODE>
+static void launch_rows32x2_mode(const Row32Args &ra, int np, int nn, const float *x, int64_t ldx, float *y,
+                                 int64_t ldy, double alpha, const double *coef, hipStream_t s)
+{
+    // 8-byte units where every row starts on 8 bytes
+    bool vec = ((uintptr_t)x % 8 == 0) && ((uintptr_t)y % 8 == 0) && ldx % 2 == 0 && ldy % 2 == 0;
+    if (ra.xc)
+        vec = vec && (uintptr_t)ra.xc % 8 == 0 && ra.ldc % 2 == 0;
+    const int64_t units = vec ? ra.dim_dn / 2 : ra.dim_dn;
+    const int need = (int)((units + kRowThreads - 1) / kRowThreads);
+    if (need > (vec ? 7 : 13))
+        fail(HUBBARD_EDEVICE, "row too long for the FP32 row-pair pass");
+    if (np > 4 || nn > 8)
+        fail(HUBBARD_EDEVICE, "too many hops per column for the FP32 row-pair pass");
+    if (vec)
+        launch_rows32x2_groups<MODE, true, 7>(ra, np, nn, x, ldx, y, ldy, alpha, coef, s);
+    else
+        launch_rows32x2_groups<MODE, false, 13>(ra, np, nn, x, ldx, y, ldy, alpha, coef, s);
+}
+
+static void launch_rows32x2(const HvArgs &a, const float *x, int64_t ldx, float *y, int64_t ldy, int mode,
+                            double alpha, const double *coef, hipStream_t s, float *xc, int64_t ldc, float *yo,
+                            int64_t ldyo)
+{
+    Row32Args ra;
+    ra.pidx = a.dn_pidx;
+    ra.nidx = a.dn_nidx;
+    ra.pn = a.dn_pn;
+    ra.states_up = a.states_up;
+    ra.states_dn = a.states_dn;
+    ra.dim_up = a.dim_up;
+    ra.dim_dn = (int)a.dim_dn;
+    ra.t = a.t;
+    ra.U = a.U;
+    ra.xc = xc;
+    ra.ldc = ldc;
+    ra.yo = yo;
+    ra.ldyo = ldyo;
+    const int np = a.dn_np, nn = a.dn_nn;
+    if (mode == HV_STORE)
+        launch_rows32x2_mode<HV_STORE>(ra, np, nn, x, ldx, y, ldy, alpha, coef, s);
+    else if (mode == HV_LANCZOS)
+        launch_rows32x2_mode<HV_LANCZOS>(ra, np, nn, x, ldx, y, ldy, alpha, coef, s);
+    else if (mode == HV_FUSED)
+        launch_rows32x2_mode<HV_FUSED>(ra, np, nn, x, ldx, y, ldy, alpha, coef, s);
+    else
+        launch_rows32x2_mode<HV_RESIDUAL>(ra, np, nn, x, ldx, y, ldy, alpha, coef, s);
+}
+
 template <typename T>
 int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y, int64_t ldy, T *scratch,
                int64_t lds_, int mode, double alpha, const double *coef, double *partials, hipStream_t s, T *xpad,
@@ -1568,6 +1919,10 @@ int launch_hv2(const HvArgs &a, const HvPlan &pl, const T *x, int64_t ldx, T *y,
             launch_rows64(a, pl, reinterpret_cast<const double *>(x + o), ldx, reinterpret_cast<double *>(yr + o), ldyr,
                           mode, alpha, coef, s, reinterpret_cast<double *>(ra.xc), ra.ldc, dfl,
                           reinterpret_cast<double *>(rh.yo), ldy);
+        else if (sizeof(T) == 4 && rows32x2_ok(a, mode))
+            launch_rows32x2(a, reinterpret_cast<const float *>(x + o), ldx, reinterpret_cast<float *>(yr + o), ldyr,
+                            mode, alpha, coef, s, reinterpret_cast<float *>(ra.xc), ra.ldc,
+                            reinterpret_cast<float *>(rh.yo), ldy);
         else if (pl.rows_rpb == 3)
             launch_rows_rpb<T, 3>(rh, g16, gt, pl, x + o, ldx, yr + o, ldyr, mode, alpha, coef, s);
         else if (pl.rows_rpb == 2)

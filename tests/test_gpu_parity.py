@@ -129,7 +129,7 @@ PADDED_CASES = [
     workload.problem("complete17_8u1d", 17, [(i, j) for i in range(17) for j in range(i + 1, 17)], 8, 1, 1.0, 3.0),
     workload.problem("chain13_ragged", 13, workload.chain(13), 7, 3, 1.0, 5.0),
     # down rows of 12,870 elements on the 4x4 lattice (the headline sector's
-    # row-pass launch shape: one row per workgroup in FP64, three in FP32) ...
+    # row-pass launch shape: one row per workgroup in FP64, a row pair in FP32) ...
     workload.problem("sq4x4_2u8d", 16, workload.torus(4, 4), 2, 8, 1.0, 8.0),
     workload.problem("sq4x4_1u8d_U0", 16, workload.torus(4, 4), 1, 8, 1.3, 0.0),
     # ... and 12,870 up rows in its 16 row blocks (the line pass of the headline sector)
