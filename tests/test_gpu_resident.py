@@ -31,9 +31,9 @@ def _solve(h, precision, limit, tol=1e-12):
     return r, psi
 
 
-@pytest.mark.parametrize("which,precision", [("ring14", hb.HUBBARD_FP64), ("ring8", hb.HUBBARD_FP64),
-                                             ("ring8", hb.HUBBARD_MIXED)], ids=["ring14-fp64-fused", "ring8-fp64",
-                                                                                "ring8-mixed"])
+@pytest.mark.parametrize("which,precision", [("ring14", hb.HUBBARD_FP64), ("ring14", hb.HUBBARD_MIXED),
+                                             ("ring8", hb.HUBBARD_FP64), ("ring8", hb.HUBBARD_MIXED)],
+                         ids=["ring14-fp64-fused", "ring14-mixed-fused", "ring8-fp64", "ring8-mixed"])
 def test_resident_psi_matches_replay(which, precision):
     p = workload.ring14() if which == "ring14" else workload.ring8()
     _say("resident vs replay", p.name, precision)
