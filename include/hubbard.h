@@ -149,11 +149,13 @@ int hubbard_set_precision(hubbard_h h, int precision);
 
 /* Device bytes that a solve with psi requested may hold for its resident
  * Lanczos basis (default: no limit beyond the free memory less 2 GiB).  While
- * the basis fits, every stored Lanczos vector is copied to a slot of its own as
- * the first pass runs and psi = sum_j y_j f_j is one pass over them (Sec. 2.2
- * obtains psi from the same sum); otherwise, or with 0, the slots are freed and
- * the recurrence is replayed to accumulate psi, as without the basis.  Both give
- * psi to rounding; hubbard_result.psi_resident tells which ran. */
+ * the basis fits, every Lanczos vector is kept in a slot of its own as the
+ * first pass runs (on large sectors formed there by the step itself, elsewhere
+ * copied) and psi = sum_j y_j f_j is one pass over them (Sec. 2.2 obtains psi
+ * from the same sum); otherwise, or with 0, the slots are freed and the
+ * recurrence is replayed to accumulate psi, as without the basis.  Both give
+ * psi to rounding; hubbard_result.psi_resident tells which ran.  Slots are
+ * allocated 32 vectors at a time. */
 int hubbard_set_basis_limit(hubbard_h h, size_t bytes);
 
 /* Seed of the start vector used by hubbard_lanczos (default 12043425). */
