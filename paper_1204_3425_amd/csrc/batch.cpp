@@ -8,6 +8,7 @@
 // never waits for the device inside a run.  Stopped instances skip later
 // steps; the descriptor table is rebuilt when instances join or when every
 // listed one has finished.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -378,20 +379,59 @@ bool batchable(const hubbard *h, int precision)
     return h->device >= 0 && h->tcls.empty() && (size_t)h->dn.dim * es <= 64 * 1024;
 }
 
+// The solves of one precision go to two engines on two streams (sorted by
+// size and dealt A, B, B, A, ... so both carry about the same work), stepped in
+// turn: the step launches of one stream fill the gaps between those of the
+// other.  Each solve's arithmetic is that of an engine of its own.
+namespace {
+struct Stream2 {
+    hipStream_t s = nullptr;
+    Stream2() { HUB_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+    ~Stream2()
+    {
+        if (s)
+            (void)hipStreamDestroy(s);
+    }
+};
+
+template <typename T>
+void run_pair(hubbard **hs, const hubbard_opts *opts, hubbard_result *res, const std::vector<int> &idx,
+              hipStream_t s, hipStream_t s2)
+{
+    if (idx.empty())
+        return;
+    // the second stream starts after the work already queued on the first
+    hipEvent_t ev;
+    HUB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HUB_HIP(hipEventRecord(ev, s));
+    HUB_HIP(hipStreamWaitEvent(s2, ev, 0));
+    (void)hipEventDestroy(ev);
+    std::vector<int> order = idx;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a]->dim > hs[b]->dim; });
+    Engine<T> ea(s), eb(s2);
+    for (size_t k = 0; k < order.size(); k++) {
+        const int i = order[k];
+        ((k % 4 == 0 || k % 4 == 3) ? ea : eb).add(hs[i], opts[i], &res[i]);
+    }
+    while (!ea.empty() || !eb.empty()) {
+        if (!ea.empty())
+            ea.step();
+        if (!eb.empty())
+            eb.step();
+    }
+}
+}  // namespace
+
 void run_batch(hubbard **hs, const hubbard_opts *opts, hubbard_result *res, int n, hipStream_t s)
 {
-    Engine<double> e64(s);
-    Engine<float> e32(s);
-    for (int i = 0; i < n; i++) {
-        if (opts[i].precision == HUBBARD_FP64)
-            e64.add(hs[i], opts[i], &res[i]);
-        else
-            e32.add(hs[i], opts[i], &res[i]);
-    }
-    while (!e64.empty())
-        e64.step();
-    while (!e32.empty())
-        e32.step();
+    std::vector<int> i64, i32;
+    for (int i = 0; i < n; i++)
+        (opts[i].precision == HUBBARD_FP64 ? i64 : i32).push_back(i);
+    Stream2 s2;
+    run_pair<double>(hs, opts, res, i64, s, s2.s);
+    run_pair<float>(hs, opts, res, i32, s, s2.s);
+    // the caller's stream sees the second stream's work done (the engines
+    // synchronise their streams when they end)
 }
 
 }  // namespace hub
