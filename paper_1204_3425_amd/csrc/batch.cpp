@@ -379,45 +379,62 @@ bool batchable(const hubbard *h, int precision)
     return h->device >= 0 && h->tcls.empty() && (size_t)h->dn.dim * es <= 64 * 1024;
 }
 
-// The solves of one precision go to two engines on two streams (sorted by
-// size and dealt A, B, B, A, ... so both carry about the same work), stepped in
-// turn: the step launches of one stream fill the gaps between those of the
-// other.  Each solve's arithmetic is that of an engine of its own.
+// The solves of one precision go to kBatchStreams engines on as many streams
+// (sorted by size and dealt in snake order, 0, 1, .., k-1, k-1, .., 0, so all
+// carry about the same work), stepped in turn: the step launches of one stream
+// fill the gaps between those of the others.  Each solve's arithmetic is that
+// of an engine of its own.  Two streams: measured on 64 solves, four were
+// slower than two (more launches and host work per step for the same gaps).
+constexpr int kBatchStreams = 2;
+
 namespace {
-struct Stream2 {
-    hipStream_t s = nullptr;
-    Stream2() { HUB_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
-    ~Stream2()
+struct StreamSet {
+    hipStream_t s[kBatchStreams] = {};
+    explicit StreamSet(hipStream_t first)
     {
-        if (s)
-            (void)hipStreamDestroy(s);
+        s[0] = first;
+        for (int k = 1; k < kBatchStreams; k++)
+            HUB_HIP(hipStreamCreateWithFlags(&s[k], hipStreamNonBlocking));
+    }
+    ~StreamSet()
+    {
+        for (int k = 1; k < kBatchStreams; k++)
+            if (s[k])
+                (void)hipStreamDestroy(s[k]);
     }
 };
 
 template <typename T>
-void run_pair(hubbard **hs, const hubbard_opts *opts, hubbard_result *res, const std::vector<int> &idx,
-              hipStream_t s, hipStream_t s2)
+void run_group(hubbard **hs, const hubbard_opts *opts, hubbard_result *res, const std::vector<int> &idx,
+               const StreamSet &ss)
 {
     if (idx.empty())
         return;
-    // the second stream starts after the work already queued on the first
+    const int ne = std::min<int>(kBatchStreams, (int)idx.size());
+    // the other streams start after the work already queued on the first
     hipEvent_t ev;
     HUB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    HUB_HIP(hipEventRecord(ev, s));
-    HUB_HIP(hipStreamWaitEvent(s2, ev, 0));
+    HUB_HIP(hipEventRecord(ev, ss.s[0]));
+    for (int k = 1; k < ne; k++)
+        HUB_HIP(hipStreamWaitEvent(ss.s[k], ev, 0));
     (void)hipEventDestroy(ev);
     std::vector<int> order = idx;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a]->dim > hs[b]->dim; });
-    Engine<T> ea(s), eb(s2);
-    for (size_t k = 0; k < order.size(); k++) {
-        const int i = order[k];
-        ((k % 4 == 0 || k % 4 == 3) ? ea : eb).add(hs[i], opts[i], &res[i]);
+    std::vector<std::unique_ptr<Engine<T>>> eng;
+    for (int k = 0; k < ne; k++)
+        eng.push_back(std::make_unique<Engine<T>>(ss.s[k]));
+    for (size_t q = 0; q < order.size(); q++) {
+        const int r = (int)(q % (size_t)(2 * ne));
+        const int k = r < ne ? r : 2 * ne - 1 - r;
+        eng[(size_t)k]->add(hs[order[q]], opts[order[q]], &res[order[q]]);
     }
-    while (!ea.empty() || !eb.empty()) {
-        if (!ea.empty())
-            ea.step();
-        if (!eb.empty())
-            eb.step();
+    for (bool any = true; any;) {
+        any = false;
+        for (auto &e : eng)
+            if (!e->empty()) {
+                e->step();
+                any = true;
+            }
     }
 }
 }  // namespace
@@ -427,11 +444,11 @@ void run_batch(hubbard **hs, const hubbard_opts *opts, hubbard_result *res, int 
     std::vector<int> i64, i32;
     for (int i = 0; i < n; i++)
         (opts[i].precision == HUBBARD_FP64 ? i64 : i32).push_back(i);
-    Stream2 s2;
-    run_pair<double>(hs, opts, res, i64, s, s2.s);
-    run_pair<float>(hs, opts, res, i32, s, s2.s);
-    // the caller's stream sees the second stream's work done (the engines
-    // synchronise their streams when they end)
+    StreamSet ss(s);
+    run_group<double>(hs, opts, res, i64, ss);
+    run_group<float>(hs, opts, res, i32, ss);
+    // the engines synchronise their streams when they end, so the caller's
+    // stream sees every solve done
 }
 
 }  // namespace hub
