@@ -4,9 +4,10 @@
 //   submit -> admission (first fit in arrival order against the HBM budget and
 //   the slot limit) -> build (basis and tables on the host, then upload) ->
 //   execution -> completion queue.
-// Two executors share the device: the batch executor keeps small sectors in a
-// BatchRunner and lets newly built requests join between Lanczos steps (so
-// arrivals start while earlier requests are still iterating); the solo
+// Two executors share the device: the batch executor keeps small sectors in
+// BatchRunners (two per precision, on two streams) and lets newly built
+// requests join between Lanczos steps (so arrivals start while earlier
+// requests are still iterating); the solo
 // executor runs large sectors one at a time on a second stream with the
 // two-pass H.v.  A request's reservation covers its tables and work vectors
 // and is released when it completes.
@@ -83,7 +84,7 @@ struct hubbard_server {
     bool stop = false;
     std::string fatal;
 
-    hipStream_t s_batch = nullptr, s_solo = nullptr;
+    hipStream_t s_batch[2] = {nullptr, nullptr}, s_solo = nullptr;
     std::thread t_build, t_batch, t_solo;
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -179,16 +180,20 @@ hubbard_opts opts_of(const hubbard_request &r)
 void batch_loop(hubbard_server *S)
 {
     (void)hipSetDevice(S->device);
-    std::unique_ptr<BatchRunner> runners[2];
+    // two runners per precision (index 2 * precision slot + k) on the two batch
+    // streams, so the step launches of one fill the gaps between the other's; a
+    // joining request goes to the runner of its precision with fewer solves
+    std::unique_ptr<BatchRunner> runners[4];
     std::vector<std::unique_ptr<Job>> running;
     try {
         for (;;) {
             std::vector<std::unique_ptr<Job>> joining;
             {
                 std::unique_lock<std::mutex> lk(S->mu);
-                const bool idle = !runners[0] || runners[0]->active() == 0;
-                const bool idle2 = !runners[1] || runners[1]->active() == 0;
-                if (idle && idle2)
+                bool idle = true;
+                for (auto &rn : runners)
+                    idle = idle && (!rn || rn->active() == 0);
+                if (idle)
                     S->cv.wait(lk, [&] { return S->stop || !S->ready_batch.empty(); });
                 if (S->stop)
                     break;
@@ -198,10 +203,13 @@ void batch_loop(hubbard_server *S)
                 }
             }
             for (auto &job : joining) {
-                const int p = job->req.precision == HUBBARD_FP64 ? 0 : 1;
+                const int p0 = job->req.precision == HUBBARD_FP64 ? 0 : 2;
+                auto load = [&](int i) { return runners[i] ? runners[i]->active() : 0; };
+                const int k = load(p0 + 1) < load(p0) ? 1 : 0;
+                const int p = p0 + k;
                 if (!runners[p])
-                    runners[p] = BatchRunner::make(job->req.precision, S->s_batch);
-                job->h->stream = S->s_batch;
+                    runners[p] = BatchRunner::make(job->req.precision, S->s_batch[k]);
+                job->h->stream = S->s_batch[k];
                 try {
                     runners[p]->add(job->h, opts_of(job->req), &job->done.result);
                 } catch (const Error &e) {
@@ -243,8 +251,8 @@ void batch_loop(hubbard_server *S)
         S->stop = true;
         S->cv.notify_all();
     }
-    runners[0].reset();
-    runners[1].reset();
+    for (auto &rn : runners)
+        rn.reset();
     for (auto &job : running)
         if (job && job->h)
             hubbard_free(job->h);
@@ -329,7 +337,8 @@ int hubbard_server_create(size_t hbm_budget, int max_slots, hubbard_server_h *ou
         S->max_slots = max_slots;
         S->t0 = std::chrono::steady_clock::now();
         HUB_HIP(hipGetDevice(&S->device));
-        HUB_HIP(hipStreamCreateWithFlags(&S->s_batch, hipStreamNonBlocking));
+        for (auto &sb : S->s_batch)
+            HUB_HIP(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
         HUB_HIP(hipStreamCreateWithFlags(&S->s_solo, hipStreamNonBlocking));
         hubbard_server *raw = S.get();
         S->t_build = std::thread(build_loop, raw);
@@ -439,7 +448,8 @@ int hubbard_server_destroy(hubbard_server_h S)
             for (auto &job : *q)
                 if (job && job->h)
                     hubbard_free(job->h);
-        (void)hipStreamDestroy(S->s_batch);
+        for (auto sb : S->s_batch)
+            (void)hipStreamDestroy(sb);
         (void)hipStreamDestroy(S->s_solo);
         delete S;
         return HUBBARD_OK;
